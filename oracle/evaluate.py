@@ -1,0 +1,75 @@
+"""Rounding and evaluation of the S solutions.  TEST INFRASTRUCTURE ONLY.
+
+* Rounding (training-setting appendix): P_is <= 0.5 -> 0, P_is > 0.5 -> 1.
+* MIS (problem-specification appendix): the set size sum_i x_i and the
+  number of violated edges (both endpoints selected); a head is an
+  independent set iff it violates no edge.
+* MaxCut: cut value sum_{i<j} A_ij [x_i != x_j] (the negated QUBO objective).
+* DScore (Sec. 4.1 Evaluation Metrics):
+  2 / (N S (S-1)) * sum_{s<l} d_H(x_s, x_l), from the pairwise Hamming
+  distances themselves.
+All counts are exact integers (int64); weighted cuts are float64.
+"""
+
+from __future__ import annotations
+
+from typing import Dict
+
+import numpy as np
+
+from .objective import edges_of, sigmoid_pair
+
+
+def round_solutions(Z: np.ndarray) -> np.ndarray:
+    """X = [P > 0.5] with P = sigmoid(Z), as uint8 [N, S]."""
+    P, _ = sigmoid_pair(Z)
+    return (P > 0.5).astype(np.uint8)
+
+
+def pairwise_hamming_sum(X: np.ndarray) -> int:
+    """sum_{s<l} d_H(X[:, s], X[:, l]) computed pair by pair through a Gram matrix."""
+    Xi = X.astype(np.int64)
+    ones = Xi.sum(axis=0)
+    gram = Xi.T @ Xi
+    D = ones[:, None] + ones[None, :] - 2 * gram  # d_H for every ordered pair
+    return int(np.triu(D, k=1).sum())
+
+
+def dscore(X: np.ndarray) -> float:
+    N, S = X.shape
+    if S < 2 or N == 0:
+        return 0.0
+    return 2.0 * pairwise_hamming_sum(X) / (N * S * (S - 1))
+
+
+def evaluate_one(X: np.ndarray, graph, problem: str) -> Dict[str, object]:
+    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+    Xi = X.astype(np.int64)
+    out = {"pair_hamming": pairwise_hamming_sum(X)}
+    if problem == "mis":
+        out["size"] = Xi.sum(axis=0)
+        out["violations"] = (Xi[ei] * Xi[ej]).sum(axis=0)
+    elif problem == "maxcut":
+        differ = (Xi[ei] != Xi[ej])
+        out["cut_edges"] = differ.sum(axis=0).astype(np.int64)
+        out["cut"] = (w[:, None] * differ).sum(axis=0)
+    else:
+        raise ValueError(problem)
+    return out
+
+
+def evaluate(X: np.ndarray, graph, problem: str):
+    """Per-graph evaluation; a single graph gives a one-element list."""
+    from .objective import _slice_graph
+    gp = np.asarray(graph.graph_ptr, dtype=np.int64)
+    res = []
+    for g in range(gp.size - 1):
+        sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
+        res.append(evaluate_one(X[gp[g]:gp[g + 1]], sub, problem))
+    return res
+
+
+def best_feasible_mis(ev: Dict[str, object]) -> int:
+    """Largest independent set among the heads (0 if none is feasible)."""
+    ok = ev["violations"] == 0
+    return int(ev["size"][ok].max()) if np.any(ok) else 0

@@ -1,0 +1,210 @@
+"""Relaxed CPRA objective and its gradient, in float64.  TEST INFRASTRUCTURE ONLY.
+
+Notation follows the paper: P in [0,1]^{N x S} holds S relaxed solutions
+(heads) as columns; P = sigmoid(Z) with Z the GNN output logits (GNN
+appendix, sigmoid after the last layer).
+
+Discrete objectives (problem-specification appendix, objective table):
+  MIS:    l(x; G, lam) = -sum_i x_i + lam * sum_{(i,j) in E} x_i x_j
+  MaxCut: l(x; G)      = sum_{i<j} A_ij (2 x_i x_j - x_i - x_j)
+Each edge {i, j} is counted once (i < j).  The relaxation (Sec. 2.2) keeps
+the same multilinear polynomial with p in [0,1]^N, so it equals the
+discrete objective on every binary point.
+
+CPRA loss (Sec. 3.1, Eq. CPRA-loss-function-GNN, and Sec. 3.3,
+Eq. CPRA-loss-function-GNN-variation):
+  R(P) = sum_s l(P[:, s]; lam_s) + gamma * S(P) + nu * Psi(P)
+  S(P) = sum_{i,s} (1 - (2 P_is - 1)^alpha),  alpha even
+  Psi(P) = -S * sum_i STD_s[P_is]
+with STD the empirical (population, 1/K) standard deviation of the Notation
+section; ``ddof=1`` selects the sample form mentioned at the end of Sec. 3.3.
+
+Numerics: wherever 1 - P appears it is evaluated as sigmoid(-Z), and
+1 - t^alpha with t = 2P - 1 is evaluated through the exact factorisation
+1 - t^alpha = (1 - t)(1 + t) * sum_{k < alpha/2} t^(2k) = 4 P Q * sum t^(2k)
+with Q = 1 - P, so that saturated entries keep their relative accuracy.
+"""
+
+from __future__ import annotations
+
+from typing import Dict, Optional
+
+import numpy as np
+
+PROBLEMS = ("mis", "maxcut")
+
+
+def sigmoid_pair(Z: np.ndarray):
+    """(P, Q) = (sigmoid(Z), sigmoid(-Z)), each without cancellation."""
+    Z = np.asarray(Z, dtype=np.float64)
+    e = np.exp(-np.abs(Z))
+    inv = 1.0 / (1.0 + e)
+    P = np.where(Z >= 0, inv, e * inv)
+    Q = np.where(Z >= 0, e * inv, inv)
+    return P, Q
+
+
+def edges_of(row_ptr: np.ndarray, col_idx: np.ndarray, weight: Optional[np.ndarray] = None):
+    """Undirected edge list (i < j) with weights A_ij (1 where no weights are given)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = row_ptr.size - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    cols = np.asarray(col_idx, dtype=np.int64)
+    keep = rows < cols
+    w = np.ones(int(keep.sum()), dtype=np.float64) if weight is None else \
+        np.asarray(weight, dtype=np.float64)[keep]
+    return rows[keep], cols[keep], w
+
+
+# ---------------------------------------------------------------------------
+# Discrete objectives (objective table)
+# ---------------------------------------------------------------------------
+
+def discrete_mis(x: np.ndarray, ei, ej, w, lam: float) -> float:
+    """-sum_i x_i + lam * sum_{(i,j) in E} A_ij x_i x_j for one binary vector."""
+    x = np.asarray(x, dtype=np.float64)
+    return float(-x.sum() + lam * np.sum(w * x[ei] * x[ej]))
+
+
+def discrete_maxcut(x: np.ndarray, ei, ej, w) -> float:
+    """sum_{i<j} A_ij (2 x_i x_j - x_i - x_j) for one binary vector."""
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.sum(w * (2.0 * x[ei] * x[ej] - x[ei] - x[ej])))
+
+
+# ---------------------------------------------------------------------------
+# Relaxed objective per head, annealing term, diversity term
+# ---------------------------------------------------------------------------
+
+def relaxed_head_losses(P: np.ndarray, ei, ej, w, problem: str,
+                        lam: Optional[np.ndarray]) -> np.ndarray:
+    """l_hat(P[:, s]; C, lam_s) for every head s (the relaxation of Sec. 2.2)."""
+    P = np.asarray(P, dtype=np.float64)
+    if problem == "mis":
+        lam = np.asarray(lam, dtype=np.float64)
+        pair = np.sum(w[:, None] * P[ei] * P[ej], axis=0)
+        return -P.sum(axis=0) + lam * pair
+    if problem == "maxcut":
+        return np.sum(w[:, None] * (2.0 * P[ei] * P[ej] - P[ei] - P[ej]), axis=0)
+    raise ValueError(problem)
+
+
+def one_minus_t_pow(P: np.ndarray, Q: np.ndarray, alpha: int) -> np.ndarray:
+    """phi(P) = 1 - (2P - 1)^alpha elementwise (Lemma A.1's phi), alpha even."""
+    check_alpha(alpha)
+    t = P - Q
+    series = np.zeros_like(P)
+    for k in range(alpha // 2):
+        series = series + t ** (2 * k)
+    return 4.0 * P * Q * series
+
+
+def check_alpha(alpha: int) -> None:
+    if int(alpha) != alpha or alpha < 2 or alpha % 2:
+        raise ValueError("alpha must be an even integer >= 2")
+
+
+def entropy_term(P: np.ndarray, Q: np.ndarray, alpha: int) -> float:
+    """S(P) = sum_{i,s} (1 - (2 P_is - 1)^alpha)   (Sec. 3.1)."""
+    return float(np.sum(one_minus_t_pow(P, Q, alpha)))
+
+
+def row_std(P: np.ndarray, ddof: int = 0) -> np.ndarray:
+    """STD_s[P_is] per node i, two-pass: mean first, then squared deviations."""
+    S = P.shape[1]
+    mu = P.sum(axis=1) / S
+    dev = P - mu[:, None]
+    return np.sqrt(np.sum(dev * dev, axis=1) / (S - ddof))
+
+
+def diversity_term(P: np.ndarray, ddof: int = 0) -> float:
+    """Psi(P) = -S * sum_i STD_s[P_is]   (Sec. 3.3)."""
+    S = P.shape[1]
+    return float(-S * np.sum(row_std(P, ddof)))
+
+
+# ---------------------------------------------------------------------------
+# Total loss and gradient
+# ---------------------------------------------------------------------------
+
+def loss_terms(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
+               nu: float = 0.0, ddof: int = 0) -> Dict[str, object]:
+    """All loss terms of one graph at logits Z [N, S].
+
+    Returns {"head": l_hat_s [S], "entropy": S(P), "psi": Psi(P), "total": R}.
+    ``graph`` provides row_ptr, col_idx and weight (None = unweighted).
+    """
+    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+    P, Q = sigmoid_pair(Z)
+    head = relaxed_head_losses(P, ei, ej, w, problem, lam)
+    ent = entropy_term(P, Q, alpha)
+    psi = diversity_term(P, ddof) if P.shape[1] > 1 else 0.0
+    total = float(head.sum() + gamma * ent + nu * psi)
+    return {"head": head, "entropy": ent, "psi": psi, "total": total}
+
+
+def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: float,
+               alpha: int, nu: float = 0.0, ddof: int = 0) -> np.ndarray:
+    """dR/dP [N, S] (derived by hand from the loss above).
+
+    problem part: MIS    -1 + lam_s * sum_{j in N(i)} A_ij P_js
+                  MaxCut sum_{j in N(i)} A_ij (2 P_js - 1)
+    annealing:    gamma * d/dP (1 - (2P-1)^alpha) = -2 alpha gamma (2P-1)^(alpha-1)
+    diversity:    nu * dPsi/dP_is = -nu * S (P_is - mu_i) / ((S - ddof) sigma_i),
+                  taken as 0 where sigma_i = 0 (a subgradient of the norm).
+    """
+    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+    N, S = P.shape
+    # Neighbour sums by scattering each undirected edge to both endpoints.
+    nb = np.zeros((N, S), dtype=np.float64)
+    np.add.at(nb, ei, w[:, None] * P[ej])
+    np.add.at(nb, ej, w[:, None] * P[ei])
+    if problem == "mis":
+        g = -1.0 + np.asarray(lam, dtype=np.float64)[None, :] * nb
+    elif problem == "maxcut":
+        wdeg = np.zeros(N, dtype=np.float64)
+        np.add.at(wdeg, ei, w)
+        np.add.at(wdeg, ej, w)
+        g = 2.0 * nb - wdeg[:, None]
+    else:
+        raise ValueError(problem)
+    check_alpha(alpha)
+    t = P - Q
+    g = g - 2.0 * alpha * gamma * t ** (alpha - 1)
+    if nu != 0.0 and S > 1:
+        mu = P.sum(axis=1) / S
+        sig = row_std(P, ddof)
+        dev = P - mu[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            dpsi = np.where(sig[:, None] > 0, -S * dev / ((S - ddof) * sig[:, None]), 0.0)
+        g = g + nu * dpsi
+    return g
+
+
+def grad_wrt_Z(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
+               nu: float = 0.0, ddof: int = 0) -> np.ndarray:
+    """dR/dZ = dR/dP * P * (1 - P), with 1 - P taken as sigmoid(-Z)."""
+    P, Q = sigmoid_pair(Z)
+    return grad_wrt_P(P, Q, graph, problem, lam, gamma, alpha, nu, ddof) * P * Q
+
+
+def batched_loss_terms(Z: np.ndarray, graph, problem, lam, gamma, alpha, nu=0.0, ddof=0):
+    """Per-graph loss terms of a block-diagonal batch (graph.graph_ptr slices)."""
+    out = []
+    gp = np.asarray(graph.graph_ptr, dtype=np.int64)
+    for g in range(gp.size - 1):
+        sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
+        out.append(loss_terms(Z[gp[g]:gp[g + 1]], sub, problem, lam, gamma, alpha, nu, ddof))
+    return out
+
+
+class _Sub:
+    def __init__(self, row_ptr, col_idx, weight):
+        self.row_ptr, self.col_idx, self.weight = row_ptr, col_idx, weight
+
+
+def _slice_graph(graph, lo: int, hi: int):
+    rp = np.asarray(graph.row_ptr, dtype=np.int64)
+    a, b = rp[lo], rp[hi]
+    w = None if graph.weight is None else graph.weight[a:b]
+    return _Sub(rp[lo:hi + 1] - a, np.asarray(graph.col_idx[a:b], dtype=np.int64) - lo, w)

@@ -1,0 +1,126 @@
+"""One CPRA training step and the training loop, in float64.  TEST INFRASTRUCTURE ONLY.
+
+The loop (Sec. 3.1 with the settings of Sec. 4.1 Implementation and the
+training-setting appendix): at every epoch (one full-graph gradient step)
+compute P = sigmoid(GNN_theta(G)), the loss R with the current gamma, its
+gradient, and update theta with Adam (Kingma and Ba) or AdamW (decoupled
+weight decay).  After the last epoch the relaxed solutions are rounded.
+
+gamma schedule: the paper starts from gamma(0) < 0 and raises gamma by a
+fixed rate each epoch (Sec. 4.1 Implementation: gamma(0) = -20 for MIS,
+rate 1e-3).  ``gamma_at`` implements the linear schedule between two
+endpoints over T epochs, both endpoints included; ``gamma_paper`` the
+additive form gamma(0) + rate * t.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import evaluate, gnn, objective
+
+
+def gamma_at(t: int, T: int, gamma_start: float, gamma_end: float) -> float:
+    """Linear schedule, gamma_0 = gamma_start and gamma_{T-1} = gamma_end."""
+    if T <= 1:
+        return float(gamma_end)
+    return float(gamma_start + (gamma_end - gamma_start) * (t / (T - 1)))
+
+
+def gamma_paper(t: int, gamma0: float, rate: float) -> float:
+    return float(gamma0 + rate * t)
+
+
+def adam_update(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int,
+                lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                weight_decay: float = 0.0):
+    """One Adam step (t >= 1), in place.  weight_decay > 0 gives AdamW's decoupled decay.
+
+    m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
+    theta <- theta (1 - lr wd) - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+    """
+    m *= beta1
+    m += (1.0 - beta1) * g
+    v *= beta2
+    v += (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    if weight_decay:
+        theta *= (1.0 - lr * weight_decay)
+    theta -= lr * mhat / (np.sqrt(vhat) + eps)
+
+
+@dataclass
+class StepConfig:
+    problem: str
+    lam: Optional[np.ndarray]
+    alpha: int = 2
+    nu: float = 0.0
+    ddof: int = 0
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    weight_decay: float = 0.0
+
+
+def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float):
+    """Forward, loss terms (per graph of a batch) and all parameter gradients."""
+    Z, cache = gnn.forward(params, M)
+    gp = np.asarray(graph.graph_ptr, dtype=np.int64)
+    if gp.size > 2:
+        terms = objective.batched_loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
+                                             cfg.nu, cfg.ddof)
+        dZ = np.zeros_like(Z)
+        for g in range(gp.size - 1):
+            sub = objective._slice_graph(graph, int(gp[g]), int(gp[g + 1]))
+            dZ[gp[g]:gp[g + 1]] = objective.grad_wrt_Z(Z[gp[g]:gp[g + 1]], sub, cfg.problem,
+                                                       cfg.lam, gamma, cfg.alpha, cfg.nu, cfg.ddof)
+    else:
+        terms = [objective.loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
+                                      cfg.nu, cfg.ddof)]
+        dZ = objective.grad_wrt_Z(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha, cfg.nu,
+                                  cfg.ddof)
+    grads = gnn.backward(params, M, cache, dZ)
+    return Z, terms, dZ, grads
+
+
+class AdamState:
+    def __init__(self, params):
+        self.m = {"emb": np.zeros_like(params["emb"]),
+                  "layers": [{k: np.zeros_like(v) for k, v in L.items()} for L in params["layers"]]}
+        self.v = {"emb": np.zeros_like(params["emb"]),
+                  "layers": [{k: np.zeros_like(v) for k, v in L.items()} for L in params["layers"]]}
+        self.t = 0
+
+    def step(self, params, grads, cfg: StepConfig):
+        self.t += 1
+        adam_update(params["emb"], grads["emb"], self.m["emb"], self.v["emb"], self.t, cfg.lr,
+                    cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay)
+        for L, G, Mm, Vv in zip(params["layers"], grads["layers"], self.m["layers"],
+                                self.v["layers"]):
+            for k in L:
+                adam_update(L[k], G[k], Mm[k], Vv[k], self.t, cfg.lr, cfg.beta1, cfg.beta2,
+                            cfg.eps, cfg.weight_decay)
+
+
+def solve(params_f32, graph, cfg: StepConfig, T: int, gamma_start: float, gamma_end: float,
+          record_every: int = 0) -> Dict[str, object]:
+    """Run T training steps from the given initial parameters; round and evaluate."""
+    params = gnn.to_f64(params_f32)
+    M = gnn.mean_aggregation_matrix(graph.row_ptr, graph.col_idx)
+    opt = AdamState(params)
+    history: List[Dict[str, object]] = []
+    for t in range(T):
+        gamma = gamma_at(t, T, gamma_start, gamma_end)
+        Z, terms, dZ, grads = loss_and_grads(params, M, graph, cfg, gamma)
+        if record_every and (t % record_every == 0 or t == T - 1):
+            history.append({"t": t, "gamma": gamma, "terms": terms})
+        opt.step(params, grads, cfg)
+    Z, _ = gnn.forward(params, M)
+    X = evaluate.round_solutions(Z)
+    ev = evaluate.evaluate(X, graph, cfg.problem)
+    return {"Z": Z, "X": X, "eval": ev, "params": params, "history": history}

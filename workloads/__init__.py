@@ -1,0 +1,20 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle and the benchmarks.
+
+This package holds input generation only: random graphs in CSR form, the
+seeded initial parameters of the GNN and the named workload presets (sizes,
+penalty grids, schedules).  It contains none of the method's arithmetic (no
+loss, no gradient, no aggregation), so that the oracle and the GPU path can
+both consume it without sharing any computation.
+"""
+
+from .graphs import (  # noqa: F401
+    CSRGraph,
+    csr_from_edges,
+    random_regular_graph,
+    erdos_renyi_graph,
+    disjoint_union,
+    induced_subgraph,
+    bfs_ball,
+)
+from .params import init_params, param_shapes  # noqa: F401
+from .presets import PRESETS, Preset, get_preset  # noqa: F401
