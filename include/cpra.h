@@ -1,0 +1,295 @@
+/*
+ * cpra.h -- C ABI of libcpra, the MI355X (gfx950) implementation of the
+ * CPRA training step: S relaxed solutions of one combinatorial problem
+ * (or a block-diagonal batch of instances) trained at once by a GNN.
+ *
+ * Paper: Ichikawa & Iwashita, "Continuous Parallel Relaxation for Finding
+ * Diverse Solutions in Combinatorial Optimization Problems", TMLR 2025.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are row-major float32 with an explicit leading dimension
+ *   (elements between consecutive rows).  Node-by-head matrices are [N, S]
+ *   with one node's S heads contiguous.
+ * - Pointers documented as "device" must point to device memory owned by
+ *   the caller; the library borrows them for the duration of the
+ *   stream-ordered work it enqueues and never frees them.  "Host" pointers
+ *   are read synchronously before the call returns.
+ * - The library allocates no device memory.  Entry points that need
+ *   scratch take a caller-owned workspace (ws, ws_bytes) sized by the
+ *   matching *_workspace_bytes query; the workspace must stay untouched
+ *   until the enqueued work completes.
+ * - Every call is asynchronous with respect to the host and ordered on
+ *   `stream` (a hipStream_t; NULL means the null stream).  Argument errors
+ *   are detected on the host and returned synchronously, before any work is
+ *   enqueued.  A launch failure returns CPRA_ERR_HIP; a device fault is
+ *   reported by HIP on a later synchronisation.
+ * - After a non-OK return, cpra_last_error_message() (thread-local) says
+ *   what was wrong.
+ * - Results are deterministic: no floating-point atomics; every reduction
+ *   runs in a fixed order, so identical inputs give identical bits.
+ */
+#ifndef CPRA_H
+#define CPRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPRA_ABI_VERSION 1
+
+typedef void* cpra_stream_t; /* hipStream_t */
+
+typedef enum {
+  CPRA_OK = 0,
+  CPRA_ERR_NULL = 1,       /* a required pointer is NULL */
+  CPRA_ERR_SHAPE = 2,      /* a size or leading dimension is inconsistent */
+  CPRA_ERR_CSR = 3,        /* the graph is not a valid symmetric simple CSR */
+  CPRA_ERR_PARAM = 4,      /* a method parameter is out of its domain */
+  CPRA_ERR_OVERFLOW = 5,   /* a size does not fit the int32 indexing used on device */
+  CPRA_ERR_WORKSPACE = 6,  /* workspace missing or smaller than the query returned */
+  CPRA_ERR_HIP = 7,        /* a HIP runtime call or kernel launch failed */
+  CPRA_ERR_NONFINITE = 8   /* a host-side float parameter is NaN or infinite */
+} cpra_status;
+
+enum { CPRA_MIS = 0, CPRA_MAXCUT = 1 };   /* problems of the objective table */
+enum { CPRA_GCN = 0, CPRA_SAGE = 1 };     /* layer forms of the GNN appendix */
+
+/* Version of this ABI (CPRA_ABI_VERSION of the built library). */
+int32_t cpra_abi_version(void);
+/* Static name of a status code. */
+const char* cpra_status_string(cpra_status status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* cpra_last_error_message(void);
+
+/* ------------------------------------------------------------------------
+ * Graph.  Sec. 1 (Notation): an undirected graph G(V, E) with adjacency A,
+ * A_ij > 0 on edges.  Stored as symmetric CSR: row i lists the neighbours
+ * of node i in strictly increasing order, no self loops, j in row i iff i in
+ * row j (with equal weight).  nnz = 2|E|.  A block-diagonal union of
+ * n_graphs instances carries their node offsets in graph_ptr.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_nodes;          /* N >= 0 */
+  int32_t n_graphs;         /* >= 1 */
+  int64_t nnz;              /* < 2^31 */
+  const int32_t* row_ptr;   /* device [N+1] */
+  const int32_t* col_idx;   /* device [nnz] */
+  const int32_t* graph_ptr; /* device [n_graphs+1] node offsets; NULL iff n_graphs == 1 */
+  const float* weight;      /* device [nnz] A_ij, or NULL for A_ij = 1 */
+  const float* inv_deg;     /* device [N] 1/|N(i)| (0 for isolated nodes), from cpra_csr_prepare */
+  const float* wdeg;        /* device [N] sum_j A_ij, from cpra_csr_prepare */
+} cpra_csr;
+
+/* Host-side validation of a CSR (host pointers).  Checks row_ptr[0] = 0,
+ * monotone rows, row_ptr[N] = nnz, indices in range, rows strictly
+ * increasing, no self loop, symmetry of structure and weights, finite
+ * weights.  O(nnz log d).  Returns CPRA_ERR_CSR (with the first offending
+ * row in the message), CPRA_ERR_OVERFLOW or CPRA_ERR_NULL. */
+cpra_status cpra_csr_validate_host(int32_t n_nodes, int64_t nnz, const int32_t* row_ptr,
+                                   const int32_t* col_idx, const float* weight);
+
+/* Fills inv_deg[N] = 1/|N(i)| (0 if isolated) -- the row scaling of the mean
+ * aggregation in the GNN appendix -- and wdeg[N] = sum_j A_ij, the linear
+ * coefficient of the MaxCut objective.  Reads g->row_ptr and g->weight only
+ * (g->inv_deg / g->wdeg may still be NULL).  Either output may be NULL. */
+cpra_status cpra_csr_prepare(const cpra_csr* g, float* inv_deg, float* wdeg, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Mean aggregation (GNN appendix: Aggregate step with the 1/|N(v)|
+ * normalisation of the GCN equation).  M = D^-1 A over the neighbour set
+ * (edge weights are not used here).
+ *   transpose = 0:  Y[i,:] = add[i,:] + bias + inv_deg_i * sum_{j in N(i)} X[j,:]
+ *   transpose = 1:  Y[j,:] = add[j,:] + bias + sum_{i in N(j)} inv_deg_i * X[i,:]   (M^T X)
+ * then optionally ReLU (relu != 0), then optionally masked:
+ *   Y[i,c] = 0 where mask[i,c] <= 0 (mask [N, width] with leading dim ld_mask).
+ * X [N, width] (ldx), Y [N, width] (ldy); add (ld_add), bias [width] and
+ * mask may be NULL.  add may equal Y (in place); X must not overlap Y.
+ * Requires g->inv_deg. */
+cpra_status cpra_aggregate_mean(const cpra_csr* g, int32_t transpose, int32_t width,
+                                const float* X, int64_t ldx, float* Y, int64_t ldy,
+                                const float* add, int64_t ld_add, const float* bias,
+                                int32_t relu, const float* mask, int64_t ld_mask,
+                                cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Dense FP32 GEMM on the MFMA units (the GNN's weight products):
+ *   C[M,N] = act( op(A) op(B) + beta * C + bias[N] )
+ * op(A) is [M,K]: trans_a = 0 -> A stored [M,K] (lda >= K); 1 -> A stored [K,M].
+ * op(B) is [K,N]: trans_b = 0 -> B stored [K,N] (ldb >= N); 1 -> B stored [N,K].
+ * act = ReLU if relu != 0.  bias may be NULL.  FP32 inputs, FP32 accumulate.
+ * Workspace: cpra_gemm_workspace_bytes (split-K partial tiles; may be 0). */
+size_t cpra_gemm_workspace_bytes(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K);
+cpra_status cpra_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                      const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
+                      float* C, int64_t ldc, const float* bias, int32_t relu,
+                      void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Relaxed CPRA objective and its gradient (Sec. 3.1 Eq. CPRA-loss-function-GNN,
+ * Sec. 3.2 penalty-diversified form, Sec. 3.3 Eq. CPRA-loss-function-GNN-variation,
+ * objective table of the problem-specification appendix):
+ *   P = sigmoid(Z),
+ *   R = sum_s l_s(P[:,s]) + gamma * sum_{i,s} (1 - (2 P_is - 1)^alpha) + nu * Psi(P),
+ *   MIS:    l_s = -sum_i P_is + lambda_s * sum_{i<j} A_ij P_is P_js
+ *   MaxCut: l_s = sum_{i<j} A_ij (2 P_is P_js - P_is - P_js)
+ *   Psi    = -S * sum_i STD_s[P_is]  (population STD, or sample STD if std_ddof = 1)
+ * Output dZ = dR/dZ and, per graph g of the batch, terms[g*(S+2) + c]:
+ *   c < S: l_c of graph g;  c = S: sum of (1-(2P-1)^alpha) over the graph;
+ *   c = S+1: Psi of the graph.  R = sum_s terms[s] + gamma*terms[S] + nu*terms[S+1].
+ * Per-node work is FP32; the cross-block sums of the terms are FP64.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t problem;        /* CPRA_MIS or CPRA_MAXCUT */
+  int32_t S;              /* heads, 1 <= S <= 1024 */
+  int32_t alpha;          /* even, 2 <= alpha <= 64 */
+  int32_t std_ddof;       /* 0 or 1 (needs S > std_ddof) */
+  float gamma;            /* annealing weight, used when step_counter is NULL */
+  float nu;               /* diversity weight */
+  const float* lambda;    /* device [S] penalty grid (MIS); ignored for MaxCut */
+  /* Optional device-side schedule for captured graphs: when step_counter is
+   * non-NULL, gamma = gamma_start + (gamma_end - gamma_start) * min(t, T-1)/(T-1)
+   * with t = *step_counter, evaluated in FP64 on the device. */
+  const int32_t* step_counter;
+  float gamma_start, gamma_end;
+  int32_t T;
+} cpra_loss_cfg;
+
+size_t cpra_loss_workspace_bytes(const cpra_csr* g, const cpra_loss_cfg* cfg);
+/* Z [N,S] (ldz >= S), P = sigmoid(Z) [N,S] (ldp) or NULL to have it computed
+ * into the workspace, dZ [N,S] (lddz) or NULL for the forward terms only,
+ * terms [n_graphs*(S+2)] doubles or NULL.  Requires g->wdeg for MaxCut. */
+cpra_status cpra_loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg,
+                              const float* Z, int64_t ldz, const float* P, int64_t ldp,
+                              float* dZ, int64_t lddz, double* terms,
+                              void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* P[i,s] = sigmoid(Z[i,s]) (GNN appendix: sigmoid after the last layer). */
+cpra_status cpra_sigmoid(int32_t N, int32_t S, const float* Z, int64_t ldz, float* P, int64_t ldp,
+                         cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The GNN P_theta(G) (GNN and architecture appendices):
+ *   h^0 = trainable embedding [N, in_dim];
+ *   h^k = act(Wn^k * mean_{u in N(v)} h_u^{k-1} + Ws^k h_v^{k-1} (+ b^k for SAGE));
+ *   act = ReLU for every layer but the last; the last has S outputs (logits Z).
+ * Widths: layer 1 maps in_dim -> hidden, middle layers hidden -> hidden,
+ * the last maps to S (n_layers = 1 maps in_dim -> S).
+ *
+ * Flat parameter layout (float32), offsets from cpra_model_param_offsets:
+ *   [embedding N*in_dim] then per layer k: Ws [out_k*in_k], Wn [out_k*in_k],
+ *   b [out_k] (SAGE only; absent for GCN).  Each matrix row-major [out, in].
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t layer_kind; /* CPRA_GCN (no bias) or CPRA_SAGE (one bias per layer) */
+  int32_t n_layers;   /* >= 1 */
+  int32_t in_dim;     /* embedding width (>= 1) */
+  int32_t hidden;     /* hidden width (>= 1) */
+  int32_t S;          /* output width = heads (>= 1) */
+  int32_t recompute;  /* 1: backward recomputes neighbour aggregates instead of keeping them */
+} cpra_model_cfg;
+
+/* Total float count including the embedding; -1 on invalid config. */
+int64_t cpra_model_param_count(const cpra_model_cfg* cfg, int32_t n_nodes);
+/* offsets[0] = embedding, then 3 per layer (Ws, Wn, b; b = -1 for GCN); host array
+ * of 1 + 3*n_layers int64 entries. */
+cpra_status cpra_model_param_offsets(const cpra_model_cfg* cfg, int32_t n_nodes, int64_t* offsets);
+/* Bytes of activation storage kept from forward to backward plus backward scratch. */
+size_t cpra_model_workspace_bytes(const cpra_csr* g, const cpra_model_cfg* cfg);
+/* Z [N,S] (ldz >= S).  Saves the activations the backward needs in ws. */
+cpra_status cpra_model_forward(const cpra_csr* g, const cpra_model_cfg* cfg, const float* params,
+                               float* Z, int64_t ldz, void* ws, size_t ws_bytes,
+                               cpra_stream_t stream);
+/* Hand-written backward: grads (same layout as params, fully overwritten) of a
+ * scalar loss whose gradient w.r.t. Z is dZ, using the activations that the
+ * immediately preceding cpra_model_forward on the same ws saved. */
+cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, const float* params,
+                                const float* dZ, int64_t lddz, float* grads,
+                                void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Adam / AdamW (Sec. 4.1 Implementation and the training-setting appendix;
+ * Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ *   p = p (1 - lr wd) - lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps),  t >= 1.
+ * With step_counter non-NULL, t = *step_counter + 1 is read on the device.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double lr, beta1, beta2, eps, weight_decay; /* 1 - beta is formed in FP64 */
+} cpra_adam_cfg;
+
+cpra_status cpra_adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
+                           const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
+                           cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * One full CPRA training step (Sec. 3.1 loop): forward, sigmoid, loss and
+ * dZ, hand-written backward, Adam over all parameters (embedding included).
+ * With step_counter non-NULL, gamma and Adam's t come from the device
+ * counter and the step ends by incrementing it, so the same enqueued work
+ * can be captured once and replayed for every step.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  cpra_model_cfg model;
+  cpra_loss_cfg loss;
+  cpra_adam_cfg adam;
+} cpra_step_cfg;
+
+size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg);
+/* params, grads, m, v: flat [cpra_model_param_count]; Z, dZ: [N,S] contiguous;
+ * terms: [n_graphs*(S+2)] doubles or NULL; t >= 1 used when step_counter is NULL
+ * (then cfg->loss.gamma is this step's gamma). */
+cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* params,
+                            float* grads, float* m, float* v, float* Z, float* dZ, double* terms,
+                            int32_t t, int32_t* step_counter, void* ws, size_t ws_bytes,
+                            cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Rounding and evaluation (training-setting appendix: P <= 0.5 -> 0,
+ * P > 0.5 -> 1, evaluated exactly as Z > 0; objective table; Sec. 4.1
+ * Evaluation Metrics; Proposition 3.2).  Per graph g and head s:
+ *   MIS:    value = |{i : x_is = 1}|,  violations = |{i<j in E : x_is = x_js = 1}|
+ *   MaxCut: value = |{i<j in E : x_is != x_js}| (cut edges), violations = 0,
+ *           wvalue = sum of A_ij over cut edges (FP64, fixed-order sums)
+ *   pair_hamming[g] = sum_{s<l} d_H(x_s, x_l) = sum_i k_i (S - k_i), k_i = sum_s x_is.
+ * X [N,S] uint8 (ldx), value/violations [n_graphs*S] int64, wvalue
+ * [n_graphs*S] double, pair_hamming [n_graphs] int64: each may be NULL.
+ * Integer results are exact.
+ * ---------------------------------------------------------------------- */
+size_t cpra_round_eval_workspace_bytes(const cpra_csr* g, int32_t S);
+cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const float* Z,
+                            int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
+                            int64_t* violations, double* wvalue, int64_t* pair_hamming,
+                            void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Captured step graphs: enqueue work between begin/end on a non-null stream
+ * to record it once; launch replays it.  The only library-owned object.
+ * ---------------------------------------------------------------------- */
+typedef struct cpra_graph_s* cpra_graph;
+cpra_status cpra_capture_begin(cpra_stream_t stream);
+cpra_status cpra_capture_end(cpra_stream_t stream, cpra_graph* out);
+cpra_status cpra_graph_launch(cpra_graph graph, cpra_stream_t stream);
+cpra_status cpra_graph_destroy(cpra_graph graph);
+
+/* ------------------------------------------------------------------------
+ * Per-kernel timing for roofline measurement.  Between profile_begin and
+ * profile_end every kernel the library launches on a stream that is not
+ * being captured is bracketed by two HIP events on that stream and tagged
+ * with a kernel-family name and its algorithmic work (FLOPs for the GEMMs,
+ * compulsory HBM bytes for the memory-bound kernels).  profile_end waits for
+ * the recorded events and aggregates per family; profile_get reads family i:
+ * launches, summed event time (ms), summed FLOPs and bytes.  Profiling adds
+ * two event records per launch; it is meant for measurement runs only.
+ * ---------------------------------------------------------------------- */
+cpra_status cpra_profile_begin(void);
+cpra_status cpra_profile_end(int32_t* n_kernels);
+cpra_status cpra_profile_get(int32_t i, char* name, size_t name_len, int64_t* launches,
+                             double* total_ms, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPRA_H */

@@ -1,0 +1,253 @@
+"""Python binding of the C ABI, one function per entry point, same names.
+
+Each function only marshals arguments: torch tensors (device memory) become
+raw pointers, the current torch stream becomes the hipStream_t, and a non-OK
+status raises ``CpraError``.  All computation happens in libcpra's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (GCN, MAXCUT, MIS, SAGE, AdamCfg, CpraError, Csr, LossCfg, ModelCfg,  # noqa: F401
+                   StepCfg, call)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_f32(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.float32):
+        raise TypeError(f"{name} must be a float32 device tensor")
+
+
+class DeviceGraph:
+    """A CSR graph resident in device memory, with its prepared inv_deg and wdeg.
+
+    ``row_ptr``, ``col_idx`` (int32), optional ``weight`` (float32) and optional
+    ``graph_ptr`` (int32 node offsets of a block-diagonal batch) are host arrays.
+    """
+
+    def __init__(self, row_ptr, col_idx, weight=None, graph_ptr=None, device="cuda",
+                 validate: bool = True):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        n = row_ptr.size - 1
+        if validate:
+            csr_validate_host(row_ptr, col_idx, weight)
+        self.n = n
+        self.nnz = int(row_ptr[-1])
+        self.row_ptr = torch.from_numpy(row_ptr).to(device)
+        self.col_idx = torch.from_numpy(col_idx).to(device) if self.nnz else \
+            torch.zeros(1, dtype=torch.int32, device=device)
+        self.weight = None if weight is None else \
+            torch.from_numpy(np.ascontiguousarray(weight, dtype=np.float32)).to(device)
+        gp = None if graph_ptr is None else np.ascontiguousarray(graph_ptr, dtype=np.int32)
+        self.n_graphs = 1 if gp is None else gp.size - 1
+        self.graph_ptr = torch.from_numpy(gp).to(device) if (gp is not None and self.n_graphs > 1) else None
+        self.inv_deg = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+        self.wdeg = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+        self.csr = Csr(n, self.n_graphs, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx),
+                       _ptr(self.graph_ptr), _ptr(self.weight), None, None)
+        csr_prepare(self, self.inv_deg, self.wdeg)
+        self.csr.inv_deg = _ptr(self.inv_deg)
+        self.csr.wdeg = _ptr(self.wdeg)
+
+    @classmethod
+    def from_csr(cls, g, device="cuda", validate=True):
+        gp = g.graph_ptr if getattr(g, "graph_ptr", None) is not None and len(g.graph_ptr) > 2 else None
+        return cls(g.row_ptr, g.col_idx, g.weight, gp, device, validate)
+
+    @property
+    def ref(self):
+        return C.byref(self.csr)
+
+
+def _csr(g) -> C.c_void_p:
+    return C.byref(g.csr) if isinstance(g, DeviceGraph) else C.byref(g)
+
+
+# ---------------------------------------------------------------------------
+def abi_version() -> int:
+    return int(_lib.lib().cpra_abi_version())
+
+
+def csr_validate_host(row_ptr, col_idx, weight=None) -> None:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w = None if weight is None else np.ascontiguousarray(weight, dtype=np.float32)
+    call("cpra_csr_validate_host", rp.size - 1, int(rp[-1]), rp.ctypes.data,
+         ci.ctypes.data if ci.size else None, None if w is None else w.ctypes.data)
+
+
+def csr_prepare(g, inv_deg: Optional[torch.Tensor], wdeg: Optional[torch.Tensor], stream=None):
+    call("cpra_csr_prepare", _csr(g), _ptr(inv_deg), _ptr(wdeg), _stream(stream))
+
+
+def aggregate_mean(g, X: torch.Tensor, Y: torch.Tensor, transpose: bool = False,
+                   add: Optional[torch.Tensor] = None, bias: Optional[torch.Tensor] = None,
+                   relu: bool = False, mask: Optional[torch.Tensor] = None, width: int = None,
+                   stream=None) -> torch.Tensor:
+    width = X.shape[1] if width is None else width
+    call("cpra_aggregate_mean", _csr(g), int(transpose), width, _ptr(X), X.stride(0), _ptr(Y),
+         Y.stride(0), _ptr(add), 0 if add is None else add.stride(0), _ptr(bias), int(relu),
+         _ptr(mask), 0 if mask is None else mask.stride(0), _stream(stream))
+    return Y
+
+
+def gemm_workspace_bytes(trans_a, trans_b, M, N, K) -> int:
+    return int(_lib.lib().cpra_gemm_workspace_bytes(int(trans_a), int(trans_b), M, N, K))
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, C_out: torch.Tensor, trans_a=False, trans_b=False,
+         beta: float = 0.0, bias=None, relu=False, ws: Optional[torch.Tensor] = None, stream=None):
+    """C = act(op(A) op(B) + beta C + bias), row-major, op(A) [M,K], op(B) [K,N]."""
+    M = A.shape[1] if trans_a else A.shape[0]
+    K = A.shape[0] if trans_a else A.shape[1]
+    N = B.shape[0] if trans_b else B.shape[1]
+    if ws is None:
+        nb = gemm_workspace_bytes(trans_a, trans_b, M, N, K)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=C_out.device) if nb else None
+    call("cpra_gemm", int(trans_a), int(trans_b), M, N, K, _ptr(A), A.stride(0), _ptr(B),
+         B.stride(0), float(beta), _ptr(C_out), C_out.stride(0), _ptr(bias), int(relu), _ptr(ws),
+         0 if ws is None else ws.numel(), _stream(stream))
+    return C_out
+
+
+def make_loss_cfg(problem: int, S: int, lam: Optional[torch.Tensor], alpha: int = 2,
+                  gamma: float = 0.0, nu: float = 0.0, std_ddof: int = 0,
+                  step_counter: Optional[torch.Tensor] = None, gamma_start: float = 0.0,
+                  gamma_end: float = 0.0, T: int = 1) -> LossCfg:
+    return LossCfg(problem, S, alpha, std_ddof, gamma, nu, _ptr(lam), _ptr(step_counter),
+                   gamma_start, gamma_end, T)
+
+
+def loss_workspace_bytes(g, cfg: LossCfg) -> int:
+    return int(_lib.lib().cpra_loss_workspace_bytes(_csr(g), C.byref(cfg)))
+
+
+def loss_fwd_bwd(g, cfg: LossCfg, Z: torch.Tensor, dZ: Optional[torch.Tensor],
+                 terms: Optional[torch.Tensor], ws: torch.Tensor, P: Optional[torch.Tensor] = None,
+                 stream=None):
+    call("cpra_loss_fwd_bwd", _csr(g), C.byref(cfg), _ptr(Z), Z.stride(0), _ptr(P),
+         0 if P is None else P.stride(0), _ptr(dZ), 0 if dZ is None else dZ.stride(0),
+         _ptr(terms), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def sigmoid(Z: torch.Tensor, P: torch.Tensor, stream=None):
+    call("cpra_sigmoid", Z.shape[0], Z.shape[1], _ptr(Z), Z.stride(0), _ptr(P), P.stride(0),
+         _stream(stream))
+    return P
+
+
+def make_model_cfg(layer_kind: int, n_layers: int, in_dim: int, hidden: int, S: int,
+                   recompute: bool = False) -> ModelCfg:
+    return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute))
+
+
+def model_param_count(cfg: ModelCfg, n_nodes: int) -> int:
+    n = int(_lib.lib().cpra_model_param_count(C.byref(cfg), n_nodes))
+    if n < 0:
+        raise CpraError(4, "invalid model config")
+    return n
+
+
+def model_param_offsets(cfg: ModelCfg, n_nodes: int):
+    out = (C.c_int64 * (1 + 3 * cfg.n_layers))()
+    call("cpra_model_param_offsets", C.byref(cfg), n_nodes, out)
+    return list(out)
+
+
+def model_workspace_bytes(g, cfg: ModelCfg) -> int:
+    return int(_lib.lib().cpra_model_workspace_bytes(_csr(g), C.byref(cfg)))
+
+
+def model_forward(g, cfg: ModelCfg, params: torch.Tensor, Z: torch.Tensor, ws: torch.Tensor,
+                  stream=None):
+    call("cpra_model_forward", _csr(g), C.byref(cfg), _ptr(params), _ptr(Z), Z.stride(0),
+         _ptr(ws), ws.numel(), _stream(stream))
+    return Z
+
+
+def model_backward(g, cfg: ModelCfg, params: torch.Tensor, dZ: torch.Tensor, grads: torch.Tensor,
+                   ws: torch.Tensor, stream=None):
+    call("cpra_model_backward", _csr(g), C.byref(cfg), _ptr(params), _ptr(dZ), dZ.stride(0),
+         _ptr(grads), _ptr(ws), ws.numel(), _stream(stream))
+    return grads
+
+
+def adam_step(params, grads, m, v, cfg: AdamCfg, t: int = 1, step_counter=None, stream=None):
+    call("cpra_adam_step", params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+         C.byref(cfg), int(t), _ptr(step_counter), _stream(stream))
+
+
+def train_step_workspace_bytes(g, cfg: StepCfg) -> int:
+    return int(_lib.lib().cpra_train_step_workspace_bytes(_csr(g), C.byref(cfg)))
+
+
+def train_step(g, cfg: StepCfg, params, grads, m, v, Z, dZ, terms, ws, t: int = 1,
+               step_counter=None, stream=None):
+    call("cpra_train_step", _csr(g), C.byref(cfg), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+         _ptr(Z), _ptr(dZ), _ptr(terms), int(t), _ptr(step_counter), _ptr(ws), ws.numel(),
+         _stream(stream))
+
+
+def round_eval_workspace_bytes(g, S: int) -> int:
+    return int(_lib.lib().cpra_round_eval_workspace_bytes(_csr(g), S))
+
+
+def round_eval(g, problem: int, Z: torch.Tensor, X=None, value=None, violations=None,
+               wvalue=None, pair_hamming=None, ws=None, stream=None):
+    S = Z.shape[1]
+    if ws is None:
+        ws = torch.empty(round_eval_workspace_bytes(g, S), dtype=torch.uint8, device=Z.device)
+    call("cpra_round_eval", _csr(g), problem, S, _ptr(Z), Z.stride(0), _ptr(X),
+         0 if X is None else X.stride(0), _ptr(value), _ptr(violations), _ptr(wvalue),
+         _ptr(pair_hamming), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def capture_begin(stream) -> None:
+    call("cpra_capture_begin", stream.cuda_stream)
+
+
+def capture_end(stream) -> C.c_void_p:
+    h = C.c_void_p()
+    call("cpra_capture_end", stream.cuda_stream, C.byref(h))
+    return h
+
+
+def graph_launch(graph, stream) -> None:
+    call("cpra_graph_launch", graph, stream.cuda_stream)
+
+
+def graph_destroy(graph) -> None:
+    call("cpra_graph_destroy", graph)
+
+
+def profile_begin() -> None:
+    call("cpra_profile_begin")
+
+
+def profile_end():
+    """Stop profiling; returns {name: (launches, total_ms, flops, bytes)}."""
+    n = C.c_int32()
+    call("cpra_profile_end", C.byref(n))
+    out = {}
+    for i in range(n.value):
+        name = C.create_string_buffer(128)
+        la, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        call("cpra_profile_get", i, name, 128, C.byref(la), C.byref(ms), C.byref(fl), C.byref(by))
+        out[name.value.decode()] = (la.value, ms.value, fl.value, by.value)
+    return out

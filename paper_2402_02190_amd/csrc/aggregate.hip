@@ -1,0 +1,244 @@
+// Mean aggregation M X and its transpose M^T X over a CSR graph (GNN appendix:
+// Aggregate step with the 1/|N(v)| normalisation).
+//
+// Layout: a 64-lane wavefront holds 64/LPR rows; the LPR lanes of one row
+// cover its columns in VEC-float vectors, NC vectors per lane.  Each lane
+// walks its row's neighbour list (the index loads are uniform across the row's
+// lanes) and issues up to four independent row gathers per iteration; every
+// gathered row segment is read as contiguous, coalesced vectors.  Sums run in
+// CSR order, so results are deterministic.
+#include "common.hpp"
+
+namespace cpra {
+
+namespace {
+
+template <int VEC>
+struct Vec;
+template <>
+struct Vec<1> {
+  using T = float;
+  __device__ static T zero() { return 0.0f; }
+  __device__ static void axpy(T& acc, float s, const T& x) { acc += s * x; }
+  __device__ static void add(T& acc, const T& x) { acc += x; }
+  __device__ static void scale(T& acc, float s) { acc *= s; }
+};
+template <>
+struct Vec<2> {
+  using T = float2;
+  __device__ static T zero() { return make_float2(0.f, 0.f); }
+  __device__ static void axpy(T& acc, float s, const T& x) { acc.x += s * x.x; acc.y += s * x.y; }
+  __device__ static void add(T& acc, const T& x) { acc.x += x.x; acc.y += x.y; }
+  __device__ static void scale(T& acc, float s) { acc.x *= s; acc.y *= s; }
+};
+template <>
+struct Vec<4> {
+  using T = float4;
+  __device__ static T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ static void axpy(T& acc, float s, const T& x) {
+    acc.x += s * x.x; acc.y += s * x.y; acc.z += s * x.z; acc.w += s * x.w;
+  }
+  __device__ static void add(T& acc, const T& x) {
+    acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+  }
+  __device__ static void scale(T& acc, float s) { acc.x *= s; acc.y *= s; acc.z *= s; acc.w *= s; }
+};
+
+template <int VEC>
+__device__ inline float comp(const typename Vec<VEC>::T& v, int e) {
+  if constexpr (VEC == 1) return v;
+  else if constexpr (VEC == 2) return e == 0 ? v.x : v.y;
+  else return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+template <int VEC>
+__device__ inline void set_comp(typename Vec<VEC>::T& v, int e, float x) {
+  if constexpr (VEC == 1) v = x;
+  else if constexpr (VEC == 2) { if (e == 0) v.x = x; else v.y = x; }
+  else { if (e == 0) v.x = x; else if (e == 1) v.y = x; else if (e == 2) v.z = x; else v.w = x; }
+}
+
+struct AggArgs {
+  int n;
+  int width;
+  int lpr_log2;
+  int relu;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const float* inv_deg;
+  const float* X;
+  int64_t ldx;
+  float* Y;
+  int64_t ldy;
+  const float* add;
+  int64_t ld_add;
+  const float* bias;
+  const float* mask;
+  int64_t ld_mask;
+};
+
+template <int VEC, int NC, bool TRANS>
+__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+  using V = typename Vec<VEC>::T;
+  using O = Vec<VEC>;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lpr = 1 << a.lpr_log2;
+  const int sub = lane >> a.lpr_log2;
+  const int cl = lane & (lpr - 1);
+  const int rpw = 64 >> a.lpr_log2;
+  const int row = (blockIdx.x * 4 + wave) * rpw + sub;
+  if (row >= a.n) return;
+  const int units = a.width / VEC;
+
+  V acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = O::zero();
+
+  const int beg = a.row_ptr[row];
+  const int end = a.row_ptr[row + 1];
+  int k = beg;
+  for (; k + 4 <= end; k += 4) {
+    const int j0 = a.col_idx[k], j1 = a.col_idx[k + 1], j2 = a.col_idx[k + 2], j3 = a.col_idx[k + 3];
+    float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+    if constexpr (TRANS) {
+      s0 = a.inv_deg[j0]; s1 = a.inv_deg[j1]; s2 = a.inv_deg[j2]; s3 = a.inv_deg[j3];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int u = c * lpr + cl;
+      if (u < units) {
+        const V x0 = *reinterpret_cast<const V*>(a.X + (int64_t)j0 * a.ldx + u * VEC);
+        const V x1 = *reinterpret_cast<const V*>(a.X + (int64_t)j1 * a.ldx + u * VEC);
+        const V x2 = *reinterpret_cast<const V*>(a.X + (int64_t)j2 * a.ldx + u * VEC);
+        const V x3 = *reinterpret_cast<const V*>(a.X + (int64_t)j3 * a.ldx + u * VEC);
+        if constexpr (TRANS) {
+          O::axpy(acc[c], s0, x0); O::axpy(acc[c], s1, x1);
+          O::axpy(acc[c], s2, x2); O::axpy(acc[c], s3, x3);
+        } else {
+          O::add(acc[c], x0); O::add(acc[c], x1); O::add(acc[c], x2); O::add(acc[c], x3);
+        }
+      }
+    }
+  }
+  for (; k < end; ++k) {
+    const int j = a.col_idx[k];
+    const float s = TRANS ? a.inv_deg[j] : 1.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int u = c * lpr + cl;
+      if (u < units) {
+        const V x = *reinterpret_cast<const V*>(a.X + (int64_t)j * a.ldx + u * VEC);
+        if constexpr (TRANS) O::axpy(acc[c], s, x); else O::add(acc[c], x);
+      }
+    }
+  }
+  const float rs = TRANS ? 1.f : a.inv_deg[row];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int u = c * lpr + cl;
+    if (u >= units) continue;
+    V r = acc[c];
+    if constexpr (!TRANS) O::scale(r, rs);
+    if (a.add) O::add(r, *reinterpret_cast<const V*>(a.add + (int64_t)row * a.ld_add + u * VEC));
+    if (a.bias) O::add(r, *reinterpret_cast<const V*>(a.bias + u * VEC));
+    if (a.relu || a.mask) {
+      V mk = O::zero();
+      if (a.mask) mk = *reinterpret_cast<const V*>(a.mask + (int64_t)row * a.ld_mask + u * VEC);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        float x = comp<VEC>(r, e);
+        if (a.relu) x = fmaxf(x, 0.0f);
+        if (a.mask && !(comp<VEC>(mk, e) > 0.0f)) x = 0.0f;
+        set_comp<VEC>(r, e, x);
+      }
+    }
+    *reinterpret_cast<V*>(a.Y + (int64_t)row * a.ldy + u * VEC) = r;
+  }
+}
+
+inline bool aligned(const void* p, int bytes) {
+  return p == nullptr || (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
+}
+
+template <int VEC, bool TRANS>
+cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, int64_t nnz) {
+  // compulsory bytes: X once, Y written, add/mask read, CSR, inv_deg
+  const double nw = (double)a.n * a.width * 4.0;
+  const double bytes = nw * (2.0 + (a.add ? 1.0 : 0.0) + (a.mask ? 1.0 : 0.0)) +
+                       4.0 * (double)nnz + 8.0 * (double)a.n + 4.0;
+  ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes);
+  switch (nc) {
+#define CPRA_AGG_CASE(NCV)                                                                    \
+  case NCV:                                                                                   \
+    hipLaunchKernelGGL((k_aggregate<VEC, NCV, TRANS>), dim3(blocks), dim3(256), 0, stream, a); \
+    break;
+    CPRA_AGG_CASE(1)
+    CPRA_AGG_CASE(2)
+    CPRA_AGG_CASE(4)
+    CPRA_AGG_CASE(8)
+    CPRA_AGG_CASE(16)
+#undef CPRA_AGG_CASE
+    default:
+      CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate: width too large");
+  }
+  CPRA_CHECK_LAUNCH("aggregate");
+  return CPRA_OK;
+}
+
+}  // namespace
+
+cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
+                      float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
+                      bool relu, const float* mask, int64_t ld_mask, hipStream_t stream) {
+  if (g->n_nodes == 0 || width == 0) return CPRA_OK;
+  int vec = 1;
+  for (int v : {4, 2}) {
+    int vb = v * 4;
+    if (width % v == 0 && ldx % v == 0 && ldy % v == 0 && (add == nullptr || ld_add % v == 0) &&
+        (mask == nullptr || ld_mask % v == 0) && aligned(X, vb) && aligned(Y, vb) &&
+        aligned(add, vb) && aligned(bias, vb) && aligned(mask, vb)) {
+      vec = v;
+      break;
+    }
+  }
+  int units = width / vec;
+  int lpr = 1;
+  while (lpr < units && lpr < 64) lpr <<= 1;
+  int lpr_log2 = 0;
+  while ((1 << lpr_log2) < lpr) ++lpr_log2;
+  int need = (int)ceil_div(units, lpr);
+  int nc = 1;
+  while (nc < need) nc <<= 1;
+  if (nc > 16) CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate: width %d exceeds 4096", width);
+  AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
+            X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask};
+  int rows_per_block = 4 * (64 / lpr);
+  int blocks = (int)ceil_div(g->n_nodes, rows_per_block);
+  if (transpose) {
+    if (vec == 4) return launch_nc<4, true>(a, nc, blocks, stream, g->nnz);
+    if (vec == 2) return launch_nc<2, true>(a, nc, blocks, stream, g->nnz);
+    return launch_nc<1, true>(a, nc, blocks, stream, g->nnz);
+  }
+  if (vec == 4) return launch_nc<4, false>(a, nc, blocks, stream, g->nnz);
+  if (vec == 2) return launch_nc<2, false>(a, nc, blocks, stream, g->nnz);
+  return launch_nc<1, false>(a, nc, blocks, stream, g->nnz);
+}
+
+}  // namespace cpra
+
+extern "C" cpra_status cpra_aggregate_mean(const cpra_csr* g, int32_t transpose, int32_t width,
+                                           const float* X, int64_t ldx, float* Y, int64_t ldy,
+                                           const float* add, int64_t ld_add, const float* bias,
+                                           int32_t relu, const float* mask, int64_t ld_mask,
+                                           cpra_stream_t stream) {
+  CPRA_CHECK(cpra::check_csr(g, "aggregate_mean", true, false));
+  if (width < 0) CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate_mean: width < 0");
+  if (g->n_nodes > 0 && width > 0) {
+    if (X == nullptr || Y == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "aggregate_mean: X or Y is NULL");
+    if (ldx < width || ldy < width || (add && ld_add < width) || (mask && ld_mask < width))
+      CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate_mean: leading dimension smaller than width");
+    if (X == Y) CPRA_FAIL(CPRA_ERR_PARAM, "aggregate_mean: X must not alias Y");
+  }
+  return cpra::aggregate(g, transpose != 0, width, X, ldx, Y, ldy, add, ld_add, bias, relu != 0,
+                         mask, ld_mask, cpra::as_stream(stream));
+}

@@ -1,0 +1,155 @@
+// Internal declarations shared by the libcpra translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "cpra.h"
+
+namespace cpra {
+
+// ---- error reporting ------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define CPRA_FAIL(code, ...)         \
+  do {                               \
+    ::cpra::set_error(__VA_ARGS__);  \
+    return (code);                   \
+  } while (0)
+
+#define CPRA_CHECK(expr)                   \
+  do {                                     \
+    cpra_status _s = (expr);               \
+    if (_s != CPRA_OK) return _s;          \
+  } while (0)
+
+#define CPRA_CHECK_LAUNCH(name)                                                           \
+  do {                                                                                    \
+    hipError_t _e = hipGetLastError();                                                    \
+    if (_e != hipSuccess)                                                                 \
+      CPRA_FAIL(CPRA_ERR_HIP, "%s: kernel launch failed: %s", name, hipGetErrorString(_e)); \
+  } while (0)
+
+// Brackets one kernel launch with timing events while profiling is on
+// (see profile.hip); `flops` / `bytes` are the launch's algorithmic work.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t stream, double flops, double bytes);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  bool active_;
+  hipStream_t stream_;
+  size_t idx_ = 0;
+};
+
+inline hipStream_t as_stream(cpra_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- graph checks shared by entry points ----------------------------------
+cpra_status check_csr(const cpra_csr* g, const char* who, bool need_inv_deg, bool need_wdeg);
+
+// ---- row blocks ("items") that never cross a graph boundary ----------------
+// A reduction over rows that must be segmented by graph assigns rows to items
+// of at most `rows_per_item` consecutive rows inside one graph.  For a single
+// graph item b covers rows [b*R, min(N, (b+1)*R)).  For a batch the item
+// offsets per graph are an exclusive scan of ceil(n_g / R), computed on the
+// device into `item_ptr` [n_graphs+1].
+int64_t max_items(const cpra_csr* g, int rows_per_item);
+cpra_status launch_item_ptr(const cpra_csr* g, int rows_per_item, int32_t* item_ptr,
+                            hipStream_t stream);
+
+// Device helper: the graph and row range of item b.  Returns false when b is
+// past the last item.
+__device__ inline bool item_rows(int b, int n_graphs, int n_nodes, const int32_t* graph_ptr,
+                                 const int32_t* item_ptr, int R, int* g_out, int* r0, int* r1) {
+  if (graph_ptr == nullptr) {
+    int lo = b * R;
+    if (lo >= n_nodes) return false;
+    *g_out = 0;
+    *r0 = lo;
+    *r1 = min(n_nodes, lo + R);
+    return true;
+  }
+  if (b >= item_ptr[n_graphs]) return false;
+  int lo = 0, hi = n_graphs;  // find g with item_ptr[g] <= b < item_ptr[g+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (item_ptr[mid] <= b) lo = mid; else hi = mid;
+  }
+  int local = b - item_ptr[lo];
+  int gs = graph_ptr[lo], ge = graph_ptr[lo + 1];
+  *g_out = lo;
+  *r0 = gs + local * R;
+  *r1 = min(ge, *r0 + R);
+  return true;
+}
+
+// Fixed-order FP64 reduction of per-item partial columns into per-graph sums:
+// out[g*ncols + c] = sum over items of graph g of part[c*items_cap + item].
+cpra_status launch_segment_reduce(const cpra_csr* g, int rows_per_item, const int32_t* item_ptr,
+                                  const float* part, const double* part64, int64_t items_cap,
+                                  int ncols, double* out, hipStream_t stream);
+
+// ---- kernels used by the model orchestration ------------------------------
+struct GemmPiece {
+  const float* A;
+  const float* B;
+  int64_t lda, ldb;
+  int K;
+};
+
+struct GemmProblem {
+  GemmPiece piece[2];  // the contraction runs over piece[0].K then piece[1].K
+  int n_pieces;
+  float* C;
+  int64_t ldc;
+  int M, N;
+  const float* bias;   // [N] or null
+  const float* mask;   // [M, N] (ld_mask): output zeroed where mask <= 0; or null
+  int64_t ld_mask;
+  float beta;
+  int relu;
+};
+
+// Up to 4 independent problems in one launch, all with the same operand layout.
+// a_t: A stored [K, M]; b_t: B stored [N, K].
+size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, int n);
+cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
+                      float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
+                      bool relu, const float* mask, int64_t ld_mask, hipStream_t stream);
+
+// Deterministic column sums: out[c] = sum_i X[i, c] (+ beta * out[c]) over rows 0..M-1.
+size_t colsum_workspace_bytes(int M, int N);
+cpra_status colsum(int M, int N, const float* X, int64_t ldx, float* out, void* ws,
+                   size_t ws_bytes, hipStream_t stream);
+
+cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t ldp,
+                    hipStream_t stream);
+
+size_t loss_workspace_bytes(const cpra_csr* g, int S, bool need_p);
+cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const float* Z, int64_t ldz,
+                         const float* P, int64_t ldp, float* dZ, int64_t lddz, double* terms,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+cpra_status check_loss_cfg_public(const cpra_csr* g, const cpra_loss_cfg* cfg);
+
+cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
+                      const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
+                      hipStream_t stream);
+cpra_status check_adam_cfg(const cpra_adam_cfg* cfg);
+
+cpra_status fill_i64(int64_t* p, int64_t n, int64_t value, hipStream_t stream);
+cpra_status increment_counter(int32_t* counter, hipStream_t stream);
+
+}  // namespace cpra

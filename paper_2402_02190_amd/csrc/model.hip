@@ -1,0 +1,396 @@
+// The GNN P_theta(G) of the GNN and architecture appendices, its hand-written
+// backward, and the full CPRA training step (Sec. 3.1 loop).
+//
+// Layer k maps H [N, in] to act(M H Wn^T + H Ws^T (+ b)) [N, out].  Two
+// evaluation orders, equal in exact arithmetic:
+//  * aggregate-first (out >= in): AX = M H, then one GEMM over the K pieces
+//    (H, Ws) and (AX, Wn) with bias/ReLU in the epilogue;
+//  * linear-first (out < in, e.g. the S-wide output layer): [Ys | Yn] =
+//    H [Ws; Wn]^T by two GEMMs in one launch, then Y = Ys + M Yn + b with
+//    the ReLU in the aggregation epilogue -- the gather is out wide, not in.
+// Backward (dY = upstream gradient, masked by the ReLU of the layer's output):
+//  * aggregate-first: dWs = dY^T H, dWn = dY^T AX, G = dY [Ws | Wn],
+//    dH = G_s + M^T G_n (masked by H > 0 in the same pass);
+//  * linear-first: T = M^T dY, dWs = dY^T H, dWn = T^T H,
+//    dH = [dY | T] [Ws; Wn] (masked in the GEMM epilogue).
+// db = column sums of dY.  M^T = A D^-1 is applied by the transposed
+// aggregation (not M: the graph need not be regular).  With recompute set,
+// AX is not kept from the forward and is rebuilt in the backward.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace cpra {
+
+cpra_status check_loss_cfg_public(const cpra_csr* g, const cpra_loss_cfg* cfg);
+cpra_status check_adam_cfg(const cpra_adam_cfg* cfg);
+
+namespace {
+
+constexpr int kMaxLayers = 16;
+
+struct Layer {
+  int in, out;
+  bool lf;  // linear-first
+  int64_t off_ws, off_wn, off_b;
+};
+
+struct Plan {
+  int L;
+  bool sage, recompute;
+  int N;
+  Layer layer[kMaxLayers];
+  int64_t n_params;
+  size_t h_off[kMaxLayers];   // saved input of layer k (k >= 1)
+  size_t ax_off[kMaxLayers];  // saved M H of aggregate-first layers
+  size_t ax_scratch_off;      // recompute buffer
+  size_t yy_off, d_off[2], g_off, t_off, gemm_off, colsum_off;
+  size_t gemm_bytes, colsum_bytes;
+  size_t total;
+};
+
+cpra_status check_model_cfg(const cpra_model_cfg* cfg) {
+  if (cfg == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "model: cfg is NULL");
+  if (cfg->layer_kind != CPRA_GCN && cfg->layer_kind != CPRA_SAGE)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: unknown layer kind %d", cfg->layer_kind);
+  if (cfg->n_layers < 1 || cfg->n_layers > kMaxLayers)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: n_layers = %d outside 1..%d", cfg->n_layers, kMaxLayers);
+  if (cfg->in_dim < 1 || cfg->hidden < 1 || cfg->S < 1 || cfg->S > 1024)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: widths must be >= 1 and S <= 1024");
+  if (cfg->in_dim > 4096 || cfg->hidden > 4096)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: in_dim and hidden up to 4096 supported");
+  return CPRA_OK;
+}
+
+void make_layers(const cpra_model_cfg* cfg, int N, Plan* p) {
+  p->L = cfg->n_layers;
+  p->sage = cfg->layer_kind == CPRA_SAGE;
+  p->recompute = cfg->recompute != 0;
+  p->N = N;
+  int64_t off = (int64_t)N * cfg->in_dim;
+  int d_in = cfg->in_dim;
+  for (int k = 0; k < p->L; ++k) {
+    Layer& l = p->layer[k];
+    l.in = d_in;
+    l.out = (k == p->L - 1) ? cfg->S : cfg->hidden;
+    l.lf = l.out < l.in;
+    l.off_ws = off;
+    off += (int64_t)l.out * l.in;
+    l.off_wn = off;
+    off += (int64_t)l.out * l.in;
+    if (p->sage) {
+      l.off_b = off;
+      off += l.out;
+    } else {
+      l.off_b = -1;
+    }
+    d_in = l.out;
+  }
+  p->n_params = off;
+}
+
+// Weight-gradient GEMM shapes of layer k (for the workspace query).
+void wgrad_problems(const Plan& p, int k, GemmProblem* q) {
+  const Layer& l = p.layer[k];
+  for (int i = 0; i < 2; ++i) {
+    q[i] = GemmProblem{};
+    q[i].n_pieces = 1;
+    q[i].piece[0].K = p.N;
+    q[i].M = l.out;
+    q[i].N = l.in;
+  }
+}
+
+void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
+  make_layers(cfg, N, p);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes, 256);
+    return o;
+  };
+  const size_t f = sizeof(float);
+  int max_in_after0 = 0, max_in_af = 0, max_out_lf = 0;
+  for (int k = 0; k < p->L; ++k) {
+    const Layer& l = p->layer[k];
+    p->h_off[k] = (k >= 1) ? take((size_t)N * l.in * f) : 0;
+    if (k >= 1) max_in_after0 = std::max(max_in_after0, l.in);
+    if (!l.lf) {
+      max_in_af = std::max(max_in_af, l.in);
+      p->ax_off[k] = p->recompute ? 0 : take((size_t)N * l.in * f);
+    } else {
+      max_out_lf = std::max(max_out_lf, l.out);
+      p->ax_off[k] = 0;
+    }
+  }
+  p->ax_scratch_off = (p->recompute && max_in_af > 0) ? take((size_t)N * max_in_af * f) : 0;
+  p->yy_off = max_out_lf ? take((size_t)N * 2 * max_out_lf * f) : 0;
+  p->d_off[0] = max_in_after0 ? take((size_t)N * max_in_after0 * f) : 0;
+  p->d_off[1] = max_in_after0 ? take((size_t)N * max_in_after0 * f) : 0;
+  p->g_off = max_in_af ? take((size_t)N * 2 * max_in_af * f) : 0;
+  p->t_off = max_out_lf ? take((size_t)N * max_out_lf * f) : 0;
+  size_t gb = 0, cb = 0;
+  for (int k = 0; k < p->L; ++k) {
+    GemmProblem q[2];
+    wgrad_problems(*p, k, q);
+    gb = std::max(gb, gemm_batch_workspace_bytes(true, false, q, 2));
+    cb = std::max(cb, colsum_workspace_bytes(N, p->layer[k].out));
+  }
+  p->gemm_bytes = gb;
+  p->colsum_bytes = cb;
+  p->gemm_off = gb ? take(gb) : 0;
+  p->colsum_off = cb ? take(cb) : 0;
+  p->total = std::max<size_t>(off, 256);
+}
+
+inline float* fptr(void* ws, size_t off) {
+  return reinterpret_cast<float*>(static_cast<char*>(ws) + off);
+}
+
+cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, float* Z,
+                         int64_t ldz, void* ws, hipStream_t st) {
+  const int N = g->n_nodes;
+  const float* H = params;  // embedding
+  int64_t ldh = p.layer[0].in;
+  for (int k = 0; k < p.L; ++k) {
+    const Layer& l = p.layer[k];
+    const bool last = k == p.L - 1;
+    float* dst = last ? Z : fptr(ws, p.h_off[k + 1]);
+    const int64_t ldd = last ? ldz : l.out;
+    const float* Ws = params + l.off_ws;
+    const float* Wn = params + l.off_wn;
+    const float* b = p.sage ? params + l.off_b : nullptr;
+    if (!l.lf) {
+      float* AX = fptr(ws, p.recompute ? p.ax_scratch_off : p.ax_off[k]);
+      CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
+      GemmProblem q{};
+      q.piece[0] = GemmPiece{H, Ws, ldh, l.in, l.in};
+      q.piece[1] = GemmPiece{AX, Wn, l.in, l.in, l.in};
+      q.n_pieces = 2;
+      q.C = dst;
+      q.ldc = ldd;
+      q.M = N;
+      q.N = l.out;
+      q.bias = b;
+      q.relu = last ? 0 : 1;
+      CPRA_CHECK(gemm_batch(false, true, &q, 1, nullptr, 0, st));
+    } else {
+      float* YY = fptr(ws, p.yy_off);
+      const int64_t ldyy = 2 * l.out;
+      GemmProblem q[2] = {};
+      for (int i = 0; i < 2; ++i) {
+        q[i].piece[0] = GemmPiece{H, i == 0 ? Ws : Wn, ldh, l.in, l.in};
+        q[i].n_pieces = 1;
+        q[i].C = YY + (i == 0 ? 0 : l.out);
+        q[i].ldc = ldyy;
+        q[i].M = N;
+        q[i].N = l.out;
+      }
+      CPRA_CHECK(gemm_batch(false, true, q, 2, nullptr, 0, st));
+      CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, b, !last, nullptr,
+                           0, st));
+    }
+    H = dst;
+    ldh = ldd;
+  }
+  return CPRA_OK;
+}
+
+cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params, const float* dZ,
+                          int64_t lddz, float* grads, void* ws, hipStream_t st) {
+  const int N = g->n_nodes;
+  const float* dY = dZ;
+  int64_t lddy = lddz;
+  int ping = 0;
+  void* gemm_ws = p.gemm_bytes ? static_cast<char*>(ws) + p.gemm_off : nullptr;
+  void* col_ws = p.colsum_bytes ? static_cast<char*>(ws) + p.colsum_off : nullptr;
+  for (int k = p.L - 1; k >= 0; --k) {
+    const Layer& l = p.layer[k];
+    const float* Hk = (k == 0) ? params : fptr(ws, p.h_off[k]);
+    const int64_t ldh = l.in;
+    const float* Ws = params + l.off_ws;
+    const float* Wn = params + l.off_wn;
+    float* dWs = grads + l.off_ws;
+    float* dWn = grads + l.off_wn;
+    float* dX = (k == 0) ? grads : fptr(ws, p.d_off[ping]);
+    const int64_t lddx = l.in;
+    const float* mask = (k == 0) ? nullptr : Hk;  // H_k = ReLU output of layer k-1
+    if (p.sage)
+      CPRA_CHECK(colsum(N, l.out, dY, lddy, grads + l.off_b, col_ws, p.colsum_bytes, st));
+    if (l.lf) {
+      float* T = fptr(ws, p.t_off);
+      CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
+      GemmProblem q[2] = {};
+      for (int i = 0; i < 2; ++i) {
+        q[i].piece[0] = GemmPiece{i == 0 ? dY : T, Hk, i == 0 ? lddy : l.out, ldh, N};
+        q[i].n_pieces = 1;
+        q[i].C = i == 0 ? dWs : dWn;
+        q[i].ldc = l.in;
+        q[i].M = l.out;
+        q[i].N = l.in;
+      }
+      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
+      GemmProblem r{};
+      r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
+      r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
+      r.n_pieces = 2;
+      r.C = dX;
+      r.ldc = lddx;
+      r.M = N;
+      r.N = l.in;
+      r.mask = mask;
+      r.ld_mask = ldh;
+      CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
+    } else {
+      const float* AX;
+      if (p.recompute) {
+        float* buf = fptr(ws, p.ax_scratch_off);
+        CPRA_CHECK(aggregate(g, false, l.in, Hk, ldh, buf, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
+        AX = buf;
+      } else {
+        AX = fptr(ws, p.ax_off[k]);
+      }
+      GemmProblem q[2] = {};
+      for (int i = 0; i < 2; ++i) {
+        q[i].piece[0] = GemmPiece{dY, i == 0 ? Hk : AX, lddy, l.in, N};
+        q[i].n_pieces = 1;
+        q[i].C = i == 0 ? dWs : dWn;
+        q[i].ldc = l.in;
+        q[i].M = l.out;
+        q[i].N = l.in;
+      }
+      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
+      float* G = fptr(ws, p.g_off);
+      const int64_t ldg = 2 * l.in;
+      GemmProblem r[2] = {};
+      for (int i = 0; i < 2; ++i) {
+        r[i].piece[0] = GemmPiece{dY, i == 0 ? Ws : Wn, lddy, l.in, l.out};
+        r[i].n_pieces = 1;
+        r[i].C = G + (i == 0 ? 0 : l.in);
+        r[i].ldc = ldg;
+        r[i].M = N;
+        r[i].N = l.in;
+      }
+      CPRA_CHECK(gemm_batch(false, false, r, 2, nullptr, 0, st));
+      CPRA_CHECK(aggregate(g, true, l.in, G + l.in, ldg, dX, lddx, G, ldg, nullptr, false, mask, ldh, st));
+    }
+    dY = dX;
+    lddy = lddx;
+    ping ^= 1;
+  }
+  return CPRA_OK;
+}
+
+cpra_status check_graph_and_model(const cpra_csr* g, const cpra_model_cfg* cfg, const char* who) {
+  CPRA_CHECK(check_csr(g, who, true, false));
+  CPRA_CHECK(check_model_cfg(cfg));
+  return CPRA_OK;
+}
+
+}  // namespace
+
+}  // namespace cpra
+
+extern "C" {
+
+int64_t cpra_model_param_count(const cpra_model_cfg* cfg, int32_t n_nodes) {
+  if (cpra::check_model_cfg(cfg) != CPRA_OK || n_nodes < 0) return -1;
+  cpra::Plan p{};
+  cpra::make_layers(cfg, n_nodes, &p);
+  return p.n_params;
+}
+
+cpra_status cpra_model_param_offsets(const cpra_model_cfg* cfg, int32_t n_nodes, int64_t* offsets) {
+  CPRA_CHECK(cpra::check_model_cfg(cfg));
+  if (offsets == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "param_offsets: offsets is NULL");
+  cpra::Plan p{};
+  cpra::make_layers(cfg, n_nodes, &p);
+  offsets[0] = 0;
+  for (int k = 0; k < p.L; ++k) {
+    offsets[1 + 3 * k] = p.layer[k].off_ws;
+    offsets[2 + 3 * k] = p.layer[k].off_wn;
+    offsets[3 + 3 * k] = p.layer[k].off_b;
+  }
+  return CPRA_OK;
+}
+
+size_t cpra_model_workspace_bytes(const cpra_csr* g, const cpra_model_cfg* cfg) {
+  if (g == nullptr || cpra::check_model_cfg(cfg) != CPRA_OK) return 0;
+  cpra::Plan p{};
+  cpra::make_plan(cfg, g->n_nodes, &p);
+  return p.total;
+}
+
+cpra_status cpra_model_forward(const cpra_csr* g, const cpra_model_cfg* cfg, const float* params,
+                               float* Z, int64_t ldz, void* ws, size_t ws_bytes,
+                               cpra_stream_t stream) {
+  using namespace cpra;
+  CPRA_CHECK(check_graph_and_model(g, cfg, "model_forward"));
+  if (ldz < cfg->S) CPRA_FAIL(CPRA_ERR_SHAPE, "model_forward: ldz < S");
+  if (g->n_nodes == 0) return CPRA_OK;
+  if (params == nullptr || Z == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "model_forward: NULL buffer");
+  Plan p{};
+  make_plan(cfg, g->n_nodes, &p);
+  if (ws == nullptr || ws_bytes < p.total)
+    CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_forward: workspace %zu < %zu bytes", ws_bytes, p.total);
+  return forward_impl(g, p, params, Z, ldz, ws, as_stream(stream));
+}
+
+cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, const float* params,
+                                const float* dZ, int64_t lddz, float* grads, void* ws,
+                                size_t ws_bytes, cpra_stream_t stream) {
+  using namespace cpra;
+  CPRA_CHECK(check_graph_and_model(g, cfg, "model_backward"));
+  if (lddz < cfg->S) CPRA_FAIL(CPRA_ERR_SHAPE, "model_backward: lddz < S");
+  if (g->n_nodes == 0) return CPRA_OK;
+  if (params == nullptr || dZ == nullptr || grads == nullptr)
+    CPRA_FAIL(CPRA_ERR_NULL, "model_backward: NULL buffer");
+  Plan p{};
+  make_plan(cfg, g->n_nodes, &p);
+  if (ws == nullptr || ws_bytes < p.total)
+    CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_backward: workspace %zu < %zu bytes", ws_bytes, p.total);
+  return backward_impl(g, p, params, dZ, lddz, grads, ws, as_stream(stream));
+}
+
+size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg) {
+  if (g == nullptr || cfg == nullptr || cpra::check_model_cfg(&cfg->model) != CPRA_OK) return 0;
+  cpra::Plan p{};
+  cpra::make_plan(&cfg->model, g->n_nodes, &p);
+  return cpra::align_up(p.total, 256) + cpra::loss_workspace_bytes(g, cfg->model.S, true);
+}
+
+cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* params,
+                            float* grads, float* m, float* v, float* Z, float* dZ, double* terms,
+                            int32_t t, int32_t* step_counter, void* ws, size_t ws_bytes,
+                            cpra_stream_t stream) {
+  using namespace cpra;
+  if (cfg == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "train_step: cfg is NULL");
+  CPRA_CHECK(check_graph_and_model(g, &cfg->model, "train_step"));
+  if (cfg->loss.problem == CPRA_MAXCUT && g->n_nodes > 0 && g->wdeg == nullptr)
+    CPRA_FAIL(CPRA_ERR_NULL, "train_step: wdeg is NULL (run cpra_csr_prepare)");
+  cpra_loss_cfg lc = cfg->loss;
+  lc.step_counter = step_counter;
+  CPRA_CHECK(check_loss_cfg_public(g, &lc));
+  CPRA_CHECK(check_adam_cfg(&cfg->adam));
+  if (cfg->loss.S != cfg->model.S) CPRA_FAIL(CPRA_ERR_PARAM, "train_step: loss.S != model.S");
+  if (step_counter == nullptr && t < 1) CPRA_FAIL(CPRA_ERR_PARAM, "train_step: t must be >= 1");
+  if (g->n_nodes == 0) return CPRA_OK;
+  if (!params || !grads || !m || !v || !Z || !dZ) CPRA_FAIL(CPRA_ERR_NULL, "train_step: NULL buffer");
+  Plan p{};
+  make_plan(&cfg->model, g->n_nodes, &p);
+  const size_t model_bytes = align_up(p.total, 256);
+  const size_t need = model_bytes + loss_workspace_bytes(g, cfg->model.S, true);
+  if (ws == nullptr || ws_bytes < need)
+    CPRA_FAIL(CPRA_ERR_WORKSPACE, "train_step: workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = as_stream(stream);
+  const int S = cfg->model.S;
+  CPRA_CHECK(forward_impl(g, p, params, Z, S, ws, st));
+  CPRA_CHECK(loss_fwd_bwd(g, &lc, Z, S, nullptr, 0, dZ, S, terms,
+                          static_cast<char*>(ws) + model_bytes, ws_bytes - model_bytes, st));
+  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st));
+  CPRA_CHECK(adam_step(p.n_params, params, grads, m, v, &cfg->adam, t, step_counter, st));
+  if (step_counter) CPRA_CHECK(increment_counter(step_counter, st));
+  return CPRA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""CPRA solver: device buffers, the training loop and decoding.
+
+The solver owns the flat parameter vector, its gradient and Adam moments,
+the logits Z and dZ, the per-graph loss terms and one workspace, all as
+torch device tensors.  Each training step is one ``cpra_train_step`` call
+(forward, loss, hand-written backward, Adam) on one stream; with
+``use_graph`` the step is captured once into a HIP graph and replayed.  The
+annealing weight gamma and Adam's step number come from a device counter
+that the step itself advances, so eager and replayed steps are identical.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import api
+from .api import DeviceGraph
+
+
+@dataclass
+class CPRAConfig:
+    problem: str = "mis"          # "mis" or "maxcut"
+    layer_kind: str = "gcn"       # "gcn" or "sage"
+    n_layers: int = 2
+    hidden: int = 32
+    S: int = 10
+    in_dim: Optional[int] = None  # embedding width (default: hidden)
+    alpha: int = 2
+    nu: float = 0.0
+    std_ddof: int = 0
+    gamma_start: float = -2.0
+    gamma_end: float = 0.1
+    T: int = 2000
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    weight_decay: float = 0.0
+    recompute: bool = False
+
+
+def gamma_schedule(t: int, T: int, g0: float, g1: float) -> float:
+    """gamma_t = g0 + (g1 - g0) * min(t, T-1) / (T-1): the device formula, on the host."""
+    if T <= 1:
+        return float(g1)
+    return float(np.float32(g0 + (g1 - g0) * (min(t, T - 1) / (T - 1))))
+
+
+class CPRASolver:
+    def __init__(self, graph: DeviceGraph, cfg: CPRAConfig, lam=None, device="cuda"):
+        if cfg.problem not in ("mis", "maxcut"):
+            raise ValueError("problem must be 'mis' or 'maxcut'")
+        self.graph = graph
+        self.cfg = cfg
+        self.device = device
+        N, S = graph.n, cfg.S
+        self.problem_id = api.MIS if cfg.problem == "mis" else api.MAXCUT
+        in_dim = cfg.hidden if cfg.in_dim is None else cfg.in_dim
+        self.model_cfg = api.make_model_cfg(api.SAGE if cfg.layer_kind == "sage" else api.GCN,
+                                            cfg.n_layers, in_dim, cfg.hidden, S, cfg.recompute)
+        if cfg.problem == "mis":
+            if lam is None:
+                raise ValueError("MIS needs a penalty grid lambda [S]")
+            lam = np.asarray(lam, dtype=np.float32)
+            if lam.shape != (S,):
+                raise ValueError("lambda must have S entries")
+            self.lam = torch.from_numpy(lam).to(device)
+        else:
+            self.lam = None
+        self.step_counter = torch.zeros(1, dtype=torch.int32, device=device)
+        self.loss_cfg = api.make_loss_cfg(self.problem_id, S, self.lam, cfg.alpha, 0.0, cfg.nu,
+                                          cfg.std_ddof, None, cfg.gamma_start, cfg.gamma_end, cfg.T)
+        self.adam_cfg = api.AdamCfg(cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay)
+        self.step_cfg = api.StepCfg(self.model_cfg, self.loss_cfg, self.adam_cfg)
+        self.n_params = api.model_param_count(self.model_cfg, N)
+        self.offsets = api.model_param_offsets(self.model_cfg, N)
+        f32 = dict(dtype=torch.float32, device=device)
+        self.params = torch.zeros(self.n_params, **f32)
+        self.grads = torch.zeros(self.n_params, **f32)
+        self.m = torch.zeros(self.n_params, **f32)
+        self.v = torch.zeros(self.n_params, **f32)
+        self.Z = torch.zeros((max(N, 1), S), **f32)
+        self.dZ = torch.zeros((max(N, 1), S), **f32)
+        self.terms = torch.zeros((graph.n_graphs, S + 2), dtype=torch.float64, device=device)
+        nb = api.train_step_workspace_bytes(graph, self.step_cfg)
+        self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+        self.t = 0
+        self._graph = None
+        self._stream = None
+
+    # -- parameters ---------------------------------------------------------
+    def load_params(self, p: Dict[str, object]) -> None:
+        """Copy {"emb", "layers": [{"Ws","Wn"[,"b"]}]} float32 arrays into the flat layout."""
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        emb = np.asarray(p["emb"], dtype=np.float32)
+        flat[: emb.size] = emb.ravel()
+        for k, L in enumerate(p["layers"]):
+            ows, own, ob = self.offsets[1 + 3 * k: 4 + 3 * k]
+            flat[ows: ows + L["Ws"].size] = np.asarray(L["Ws"], np.float32).ravel()
+            flat[own: own + L["Wn"].size] = np.asarray(L["Wn"], np.float32).ravel()
+            if ob >= 0:
+                flat[ob: ob + L["b"].size] = np.asarray(L["b"], np.float32).ravel()
+        self.params.copy_(torch.from_numpy(flat))
+        self.m.zero_()
+        self.v.zero_()
+        self.step_counter.zero_()
+        self.t = 0
+
+    def unpack(self, flat: torch.Tensor) -> Dict[str, object]:
+        """Inverse of load_params for any flat vector (params or grads), as numpy."""
+        a = flat.detach().cpu().numpy()
+        N = self.graph.n
+        in_dim = self.model_cfg.in_dim
+        out = {"emb": a[: N * in_dim].reshape(N, in_dim).copy(), "layers": []}
+        d_in = in_dim
+        for k in range(self.model_cfg.n_layers):
+            d_out = self.cfg.S if k == self.model_cfg.n_layers - 1 else self.cfg.hidden
+            ows, own, ob = self.offsets[1 + 3 * k: 4 + 3 * k]
+            L = {"Ws": a[ows: ows + d_out * d_in].reshape(d_out, d_in).copy(),
+                 "Wn": a[own: own + d_out * d_in].reshape(d_out, d_in).copy()}
+            if ob >= 0:
+                L["b"] = a[ob: ob + d_out].copy()
+            out["layers"].append(L)
+            d_in = d_out
+        return out
+
+    def loss_workspace(self) -> torch.Tensor:
+        """The loss part of the step workspace (it follows the model part)."""
+        mb = api.model_workspace_bytes(self.graph, self.model_cfg)
+        return self.ws[(mb + 255) // 256 * 256:]
+
+    # -- training -----------------------------------------------------------
+    def step(self, stream=None) -> None:
+        """One eager training step with gamma and t from the device counter."""
+        api.train_step(self.graph, self.step_cfg, self.params, self.grads, self.m, self.v, self.Z,
+                       self.dZ, self.terms, self.ws, 1, self.step_counter, stream)
+        self.t += 1
+
+    def capture(self) -> None:
+        """Record one training step into a HIP graph on a private stream."""
+        if self._graph is not None:
+            return
+        self._stream = torch.cuda.Stream()
+        self._stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self._stream):
+            api.capture_begin(self._stream)
+            try:
+                api.train_step(self.graph, self.step_cfg, self.params, self.grads, self.m, self.v,
+                               self.Z, self.dZ, self.terms, self.ws, 1, self.step_counter,
+                               self._stream)
+            finally:
+                g = api.capture_end(self._stream)
+        self._graph = g
+
+    def replay(self, n: int = 1) -> None:
+        if self._graph is None:
+            self.capture()
+        self._stream.wait_stream(torch.cuda.current_stream())
+        for _ in range(n):
+            api.graph_launch(self._graph, self._stream)
+        torch.cuda.current_stream().wait_stream(self._stream)
+        self.t += n
+
+    def run(self, steps: int, use_graph: bool = True) -> None:
+        if use_graph:
+            self.replay(steps)
+        else:
+            for _ in range(steps):
+                self.step()
+
+    def forward(self, stream=None) -> torch.Tensor:
+        """Z = GNN(params) without a parameter update."""
+        api.model_forward(self.graph, self.model_cfg, self.params, self.Z, self.ws, stream)
+        return self.Z
+
+    def evaluate(self, Z: Optional[torch.Tensor] = None) -> Dict[str, np.ndarray]:
+        """Round at P > 0.5 and evaluate every head of every graph (exact integers)."""
+        Z = self.Z if Z is None else Z
+        G, S = self.graph.n_graphs, self.cfg.S
+        dev = self.device
+        X = torch.empty((max(self.graph.n, 1), S), dtype=torch.uint8, device=dev)
+        value = torch.empty(G * S, dtype=torch.int64, device=dev)
+        viol = torch.empty(G * S, dtype=torch.int64, device=dev)
+        ph = torch.empty(G, dtype=torch.int64, device=dev)
+        wv = torch.empty(G * S, dtype=torch.float64, device=dev) if self.graph.weight is not None else None
+        api.round_eval(self.graph, self.problem_id, Z, X, value, viol, wv, ph)
+        torch.cuda.synchronize()
+        out = {"X": X[: self.graph.n].cpu().numpy(), "value": value.cpu().numpy().reshape(G, S),
+               "violations": viol.cpu().numpy().reshape(G, S), "pair_hamming": ph.cpu().numpy()}
+        if wv is not None:
+            out["wvalue"] = wv.cpu().numpy().reshape(G, S)
+        return out
+
+    def terms_host(self) -> np.ndarray:
+        torch.cuda.synchronize()
+        return self.terms.cpu().numpy()
+
+    def close(self) -> None:
+        if self._graph is not None:
+            api.graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

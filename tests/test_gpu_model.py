@@ -1,0 +1,236 @@
+"""Parity of the GNN forward, the hand-written backward, one full training step
+and whole runs against the FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import assert_close_array, assert_close_scalar, assert_update_close, need_gpu, say, to_dev
+from oracle import evaluate as oev
+from oracle import exact as oexact
+from oracle import gnn as ognn
+from oracle import objective as oobj
+from oracle import train as otrain
+from workloads import disjoint_union, erdos_renyi_graph, get_preset, init_params, random_regular_graph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def mods():
+    from paper_2402_02190_amd import api
+    from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
+    return api, CPRAConfig, CPRASolver
+
+
+def small_batch():
+    return disjoint_union([erdos_renyi_graph(60, 0.08, 1), random_regular_graph(40, 3, 2),
+                           erdos_renyi_graph(5, 0.0, 3), erdos_renyi_graph(120, 0.05, 4)])
+
+
+MODEL_CASES = [
+    # name, graph fn, kind, layers, in_dim, hidden, S
+    ("gcn2_h32_s10", lambda: random_regular_graph(100, 3, 1), "gcn", 2, 32, 32, 10),
+    ("sage2_h64_s100_af_last", lambda: erdos_renyi_graph(300, 1.5 / 299, 2), "sage", 2, 64, 64, 100),
+    ("sage2_h256_s100", lambda: random_regular_graph(2000, 5, 3), "sage", 2, 256, 256, 100),
+    ("gcn3_lf_first_batch", small_batch, "gcn", 3, 24, 16, 8),
+    ("gcn1_single_layer", lambda: random_regular_graph(50, 4, 5), "gcn", 1, 12, 12, 7),
+    ("sage3_h128_s64", lambda: random_regular_graph(1000, 20, 6), "sage", 3, 128, 128, 64),
+]
+
+
+@pytest.mark.parametrize("case", MODEL_CASES, ids=[c[0] for c in MODEL_CASES])
+def test_model_forward_backward(case):
+    api, CPRAConfig, CPRASolver = mods()
+    name, gfn, kind, L, in_dim, H, S = case
+    g = gfn()
+    say(f"model {name} n={g.n} nnz={g.nnz}")
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="maxcut", layer_kind=kind, n_layers=L, hidden=H, S=S, in_dim=in_dim)
+    sol = CPRASolver(dg, cfg)
+    p = init_params(kind, g.n, L, H, S, seed=7, in_dim=in_dim)
+    if kind == "sage":
+        for Ly in p["layers"]:
+            Ly["b"] = np.random.default_rng(1).standard_normal(Ly["b"].shape).astype(np.float32) * 0.1
+    sol.load_params(p)
+    sol.forward()
+    torch.cuda.synchronize()
+    p64 = ognn.to_f64(p)
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    Zo, cache = ognn.forward(p64, M)
+    assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what="Z")
+    dZ = np.random.default_rng(2).standard_normal((g.n, S)).astype(np.float32)
+    grads = torch.empty_like(sol.params)
+    api.model_backward(dg, sol.model_cfg, sol.params, to_dev(dZ), grads, sol.ws)
+    torch.cuda.synchronize()
+    go = ognn.backward(p64, M, cache, dZ.astype(np.float64))
+    gg = sol.unpack(grads)
+    assert_close_array(gg["emb"], go["emb"], what="d emb")
+    for k in range(L):
+        for key in go["layers"][k]:
+            assert_close_array(gg["layers"][k][key], go["layers"][k][key], what=f"d {key}{k}")
+    # recomputation gives bit-identical gradients
+    cfg_r = CPRAConfig(problem="maxcut", layer_kind=kind, n_layers=L, hidden=H, S=S, in_dim=in_dim,
+                       recompute=True)
+    sol_r = CPRASolver(dg, cfg_r)
+    sol_r.load_params(p)
+    sol_r.forward()
+    grads_r = torch.empty_like(sol.params)
+    api.model_backward(dg, sol_r.model_cfg, sol_r.params, to_dev(dZ), grads_r, sol_r.ws)
+    torch.cuda.synchronize()
+    assert torch.equal(sol_r.Z, sol.Z)
+    assert torch.equal(grads_r, grads)
+
+
+def _oracle_step(p64, g, preset_like, gamma):
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    return otrain.loss_and_grads(p64, M, g, preset_like, gamma)
+
+
+@pytest.mark.parametrize("pname", ["C1", "C3s_small", "sage_mis"])
+def test_train_step_teacher_forced(pname):
+    api, CPRAConfig, CPRASolver = mods()
+    if pname == "C1":
+        pr = get_preset("C1")
+        g = pr.graph()
+        cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=32, S=10, T=2000)
+        lam = pr.lam
+    elif pname == "C3s_small":
+        g = small_batch()
+        cfg = CPRAConfig(problem="maxcut", layer_kind="gcn", n_layers=2, hidden=64, S=32, nu=0.1,
+                         T=2000)
+        lam = None
+    else:
+        g = random_regular_graph(2000, 5, 9)
+        cfg = CPRAConfig(problem="mis", layer_kind="sage", n_layers=2, hidden=256, S=100, T=5000)
+        lam = np.logspace(-1, 1, 100).astype(np.float32)
+    say(f"train_step {pname} n={g.n}")
+    dg = api.DeviceGraph.from_csr(g)
+    sol = CPRASolver(dg, cfg, lam)
+    p = init_params(cfg.layer_kind, g.n, cfg.n_layers, cfg.hidden, cfg.S, seed=3)
+    sol.load_params(p)
+    ocfg = otrain.StepConfig(problem=cfg.problem, lam=None if lam is None else lam.astype(np.float64),
+                             alpha=2, nu=cfg.nu, lr=cfg.lr)
+    from paper_2402_02190_amd.solver import gamma_schedule
+    for round_ in range(3):
+        t = sol.t
+        p_before = sol.unpack(sol.params)
+        m_before = sol.unpack(sol.m)
+        v_before = sol.unpack(sol.v)
+        sol.step()
+        torch.cuda.synchronize()
+        gamma = gamma_schedule(t, cfg.T, cfg.gamma_start, cfg.gamma_end)
+        p64 = ognn.to_f64(p_before)
+        Zo, terms_o, dZo, go = _oracle_step(p64, g, ocfg, gamma)
+        assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what=f"[{t}] Z")
+        assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what=f"[{t}] dZ")
+        T_gpu = sol.terms.cpu().numpy()
+        for gi, to in enumerate(terms_o):
+            for s in range(cfg.S):
+                assert_close_scalar(T_gpu[gi, s], to["head"][s], abs(to["head"][s]) + 1.0 + 1e-9,
+                                    what="l_s")
+            assert_close_scalar(T_gpu[gi, cfg.S], to["entropy"], to["entropy"], what="S(P)")
+            assert_close_scalar(T_gpu[gi, cfg.S + 1], to["psi"], abs(to["psi"]), what="Psi")
+        gg = sol.unpack(sol.grads)
+        assert_close_array(gg["emb"], go["emb"], what=f"[{t}] d emb")
+        for k in range(cfg.n_layers):
+            for key in go["layers"][k]:
+                assert_close_array(gg["layers"][k][key], go["layers"][k][key], what=f"[{t}] d{key}{k}")
+        # Adam from the GPU's own gradient, in FP64, over every parameter array
+        pn = ognn.to_f64(p_before)
+        mo, vo = ognn.to_f64(m_before), ognn.to_f64(v_before)
+        g64 = ognn.to_f64(gg)
+        after = sol.unpack(sol.params)
+        otrain.adam_update(pn["emb"], g64["emb"], mo["emb"], vo["emb"], t + 1, cfg.lr)
+        assert_update_close(after["emb"], p_before["emb"], pn["emb"], what=f"[{t}] emb update")
+        for k in range(cfg.n_layers):
+            for key in pn["layers"][k]:
+                otrain.adam_update(pn["layers"][k][key], g64["layers"][k][key], mo["layers"][k][key],
+                                   vo["layers"][k][key], t + 1, cfg.lr)
+                assert_update_close(after["layers"][k][key], p_before["layers"][k][key],
+                                    pn["layers"][k][key], what=f"[{t}] {key}{k} update")
+        sol.run(5, use_graph=False)
+
+
+def test_graph_replay_is_bit_identical_to_eager():
+    api, CPRAConfig, CPRASolver = mods()
+    pr = get_preset("C1")
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=32, S=10, T=2000)
+    p = init_params("gcn", g.n, 2, 32, 10, seed=4)
+    a = CPRASolver(dg, cfg, pr.lam)
+    b = CPRASolver(dg, cfg, pr.lam)
+    a.load_params(p)
+    b.load_params(p)
+    a.run(25, use_graph=False)
+    b.run(10, use_graph=True)
+    b.run(15, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.params, b.params)
+    assert torch.equal(a.terms, b.terms)
+    assert int(b.step_counter.item()) == 25
+
+
+def test_autograd_function_matches_backward():
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.autograd import CPRALoss
+    g = random_regular_graph(200, 3, 11)
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="mis", layer_kind="sage", n_layers=2, hidden=16, S=6)
+    lam = np.linspace(0.5, 3, 6).astype(np.float32)
+    sol = CPRASolver(dg, cfg, lam)
+    p = init_params("sage", g.n, 2, 16, 6, seed=2)
+    sol.load_params(p)
+    params = sol.params.clone().requires_grad_(True)
+    R = CPRALoss.apply(params, sol, -0.5)
+    R.backward()
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    ocfg = otrain.StepConfig(problem="mis", lam=lam.astype(np.float64))
+    Zo, terms, dZo, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, -0.5)
+    assert abs(float(R) - terms[0]["total"]) <= 1e-5 * (np.abs(terms[0]["head"]).sum() + 0.5 * terms[0]["entropy"])
+    gg = sol.unpack(params.grad)
+    assert_close_array(gg["emb"], go["emb"], what="autograd d emb")
+    assert_close_array(gg["layers"][1]["Wn"], go["layers"][1]["Wn"], what="autograd dWn1")
+
+
+def test_c1_end_to_end_against_oracle_and_exact_optimum():
+    api, CPRAConfig, CPRASolver = mods()
+    pr = get_preset("C1")
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=32, S=10, T=pr.T,
+                     gamma_start=pr.gamma_start, gamma_end=pr.gamma_end, lr=pr.lr)
+    p = init_params("gcn", g.n, 2, 32, 10, seed=11)
+    sol = CPRASolver(dg, cfg, pr.lam)
+    sol.load_params(p)
+    sol.run(pr.T, use_graph=True)
+    sol.forward()
+    ev = sol.evaluate()
+    Zg = sol.Z.cpu().numpy()[: g.n].astype(np.float64)
+    # integer evaluation of the GPU's own output is bit-exact against the oracle
+    Xo = oev.round_solutions(Zg)
+    evo = oev.evaluate(Xo, g, "mis")[0]
+    assert np.array_equal(ev["X"], Xo)
+    assert np.array_equal(ev["value"][0], evo["size"])
+    assert np.array_equal(ev["violations"][0], evo["violations"])
+    # free-running FP64 oracle from the same initial bytes
+    ocfg = otrain.StepConfig(problem="mis", lam=pr.lam.astype(np.float64), lr=pr.lr)
+    ores = otrain.solve(p, g, ocfg, pr.T, pr.gamma_start, pr.gamma_end)
+    Zo = ores["Z"]
+    margin = np.abs(Zo) > 1e-4 * np.maximum(1.0, np.abs(Zo))
+    agree = np.mean((Zg > 0) == (Zo > 0))
+    per_head = [(np.array_equal((Zg[:, s] > 0), (Zo[:, s] > 0))) for s in range(10)]
+    alpha_g = oexact.mis_size_milp(g)
+    best_gpu = oev.best_feasible_mis(evo)
+    best_orc = oev.best_feasible_mis(ores["eval"][0])
+    say(f"C1: agreement {agree:.4f}, identical heads {sum(per_head)}/10, inside margin "
+        f"{int((~margin).sum())}, best GPU {best_gpu} oracle {best_orc} alpha {alpha_g}, "
+        f"min|Z| {np.abs(Zg).min():.3e}")
+    assert best_gpu <= alpha_g and best_gpu >= 0.9 * alpha_g
+    assert np.all(ev["violations"][0][pr.lam > 1.0] == 0)
+    assert agree >= 0.9
