@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its "
@@ -137,6 +138,11 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
 
+    # autotune the GEMM tile shapes on this workload's shapes (one real training step)
+    if not args.no_autotune:
+        table = sol.autotune()
+        for key, choice, us, hus in table:
+            log(f"[bench] autotune {key:40s} -> {choice:26s} {us:8.2f} us (heuristic {hus:8.2f} us)")
     # warm-up: capture once, replay W steps
     sol.capture()
     sol.replay(args.warmup)
@@ -173,6 +179,7 @@ def main():
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
                    "problem": pr.problem, "hip_graph_replay": True,
+                   "autotuned_gemm": not args.no_autotune,
                    "ms_per_step_events": ms_event},
     }
 

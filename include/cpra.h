@@ -275,6 +275,24 @@ cpra_status cpra_graph_launch(cpra_graph graph, cpra_stream_t stream);
 cpra_status cpra_graph_destroy(cpra_graph graph);
 
 /* ------------------------------------------------------------------------
+ * GEMM autotuner.  Between autotune_begin and autotune_end, every GEMM the
+ * library runs (cpra_gemm, or inside the model / train-step calls) whose
+ * problem shape has no entry in the process-wide tuning table yet is timed
+ * under each candidate tile configuration and split-K count that fits the
+ * caller's workspace; the fastest is recorded and its result left in C.
+ * Tuning synchronises the stream; launches on a stream being captured and
+ * GEMMs with beta != 0 are never tuned.  Later calls with a tuned shape use
+ * the recorded plan, others a fixed heuristic.  autotune_get reads entry i:
+ * the shape key, the chosen "config/splitN", its time and the time of the
+ * heuristic plan (microseconds).
+ * ---------------------------------------------------------------------- */
+cpra_status cpra_autotune_begin(void);
+cpra_status cpra_autotune_end(int32_t* n_entries);
+cpra_status cpra_autotune_reset(void);
+cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, char* choice,
+                              size_t choice_len, double* us, double* heuristic_us);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing for roofline measurement.  Between profile_begin and
  * profile_end every kernel the library launches on a stream that is not
  * being captured is bracketed by two HIP events on that stream and tagged

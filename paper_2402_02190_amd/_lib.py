@@ -85,6 +85,11 @@ PROTOTYPES = {
     "cpra_capture_end": (None, [P, C.POINTER(C.c_void_p)]),
     "cpra_graph_launch": (None, [P, P]),
     "cpra_graph_destroy": (None, [P]),
+    "cpra_autotune_begin": (None, []),
+    "cpra_autotune_end": (None, [C.POINTER(I32)]),
+    "cpra_autotune_reset": (None, []),
+    "cpra_autotune_get": (None, [I32, C.c_char_p, SZ, C.c_char_p, SZ, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]),
     "cpra_profile_begin": (None, []),
     "cpra_profile_end": (None, [C.POINTER(I32)]),
     "cpra_profile_get": (None, [I32, C.c_char_p, SZ, C.POINTER(I64), C.POINTER(C.c_double),

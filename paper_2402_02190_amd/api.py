@@ -251,3 +251,24 @@ def profile_end():
         call("cpra_profile_get", i, name, 128, C.byref(la), C.byref(ms), C.byref(fl), C.byref(by))
         out[name.value.decode()] = (la.value, ms.value, fl.value, by.value)
     return out
+
+
+def autotune_begin() -> None:
+    call("cpra_autotune_begin")
+
+
+def autotune_end():
+    """Stop tuning; returns [(shape key, chosen plan, us, heuristic us)] of the table."""
+    n = C.c_int32()
+    call("cpra_autotune_end", C.byref(n))
+    out = []
+    for i in range(n.value):
+        key, choice = C.create_string_buffer(256), C.create_string_buffer(64)
+        us, hus = C.c_double(), C.c_double()
+        call("cpra_autotune_get", i, key, 256, choice, 64, C.byref(us), C.byref(hus))
+        out.append((key.value.decode(), choice.value.decode(), us.value, hus.value))
+    return out
+
+
+def autotune_reset() -> None:
+    call("cpra_autotune_reset")

@@ -118,6 +118,9 @@ struct GemmProblem {
   int64_t ld_mask;
   float beta;
   int relu;
+  float* bias_grad;  // [M]: also write sum_k op(A)[row, k] (B stored [K, N] only), or null
+  float* sig_out;    // [M, N] (ld_sig): also write sigmoid(C), or null
+  int64_t ld_sig;
 };
 
 // Up to 4 independent problems in one launch, all with the same operand layout.
@@ -126,14 +129,11 @@ size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, 
 cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
+// sig_out (optional) receives sigmoid(Y) with leading dimension ld_sig.
 cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
                       float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
-                      bool relu, const float* mask, int64_t ld_mask, hipStream_t stream);
-
-// Deterministic column sums: out[c] = sum_i X[i, c] (+ beta * out[c]) over rows 0..M-1.
-size_t colsum_workspace_bytes(int M, int N);
-cpra_status colsum(int M, int N, const float* X, int64_t ldx, float* out, void* ws,
-                   size_t ws_bytes, hipStream_t stream);
+                      bool relu, const float* mask, int64_t ld_mask, hipStream_t stream,
+                      float* sig_out = nullptr, int64_t ld_sig = 0);
 
 cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t ldp,
                     hipStream_t stream);

@@ -2,17 +2,34 @@
 // dense weight products: forward X W^T, input gradient dY W and weight
 // gradient dY^T X.
 //
-// Block tile BM x BN x 16 staged through LDS (double buffered, one barrier per
-// K step), 4 wavefronts in a 2 x 2 grid, each owning (BM/64) x (BN/64) tiles
-// of 32 x 32 accumulators.  Operands stored K-contiguous are transposed into
-// the [k][mn] LDS layout while being written, so every MFMA operand read is
-// one ds_read_b32 of 32 consecutive floats per half-wave.
+// A block computes a BM x BN tile with WM x WN wavefronts, each owning
+// TM x TN = (BM/32/WM) x (BN/32/WN) accumulators of 32 x 32.  K advances in
+// BK-deep steps staged through LDS in the [k][mn] layout (double buffered,
+// one barrier per step): the next step's global loads are issued before the
+// current step's MFMAs, all MFMA operands of a step are read from LDS into
+// registers before the first MFMA of the step, and K-contiguous operands are
+// transposed while being written to LDS so every operand read is 32
+// consecutive floats per half-wavefront.  Interior tiles take unguarded
+// float4 loads (a uniform branch); edge tiles fall back to guarded loads.
 //
 // One launch runs up to four independent problems (grid.y = problem x split).
 // A problem's contraction may be split in two K pieces with separate
 // pointers, so [X | MX] [Ws | Wn]^T is a single GEMM without a concatenated
 // copy.  Split-K writes FP32 partial tiles that a second kernel sums in a
 // fixed order (deterministic), applying the epilogue.
+//
+// Weight-gradient problems may ask for the column sums of A as well (the bias
+// gradient sum_k dY[k, :]): B then gets one virtual extra column of ones,
+// whose output column is written to `bias_grad` instead of C.
+//
+// Tile shape and split count come from a table filled by the autotuner
+// (timed candidates per problem shape) or, for untuned shapes, a heuristic.
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "common.hpp"
 
 namespace cpra {
@@ -21,7 +38,6 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BK = 16;
 constexpr int kMaxProblems = 4;
 
 struct ProbDev {
@@ -39,6 +55,10 @@ struct ProbDev {
   int64_t ld_mask;
   float beta;
   int relu;
+  float* bias_grad;  // [M] column sums of op(A) via a virtual ones column of B, or null
+  float* sig_out;    // [M, N] (ld_sig): sigmoid of the result, or null
+  int64_t ld_sig;
+  int n_eff;         // N + 1 when bias_grad is set
   int tiles_m, tiles_n;
   int64_t part_off;  // float offset of this problem's split-K partials
 };
@@ -51,47 +71,59 @@ struct LaunchArgs {
   float* partial;
 };
 
-template <int R, bool KCONTIG>
+// One operand tile [BK][R] in LDS, loaded by NT threads as float4 vectors.
+template <int R, int BK, int NT, bool KCONTIG>
 struct Tile {
-  static constexpr int PAD = KCONTIG ? 2 : 4;
-  static constexpr int LD = R + PAD;  // LDS row stride (floats) of the [BK][R] tile
-  static constexpr int NV = R * BK / 4 / 256;
-  static_assert(NV >= 1, "tile too small for 256 threads");
+  static constexpr int PAD = KCONTIG ? 1 : 4;
+  static constexpr int LD = R + PAD;  // LDS row stride (floats)
+  static constexpr int NV = R * BK / 4 / NT;
+  static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
   float4 reg[NV];
 
+  // ones_col >= mn_lim: that (virtual) column reads as 1 for every valid k.
   __device__ inline void load(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim, int k0,
-                              int k_lim, bool vec_ok, int tid) {
+                              int k_lim, bool vec_ok, int tid, int ones_col) {
+    const bool full = vec_ok && (mn0 + R <= mn_lim) && (k0 + BK <= k_lim);
+    if (full) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int idx = tid + v * NT;
+        if constexpr (KCONTIG) {
+          const int r = idx / (BK / 4);
+          const int kq = (idx % (BK / 4)) * 4;
+          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(mn0 + r) * ld + k0 + kq);
+        } else {
+          const int k = idx / (R / 4);
+          const int rq = (idx % (R / 4)) * 4;
+          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(k0 + k) * ld + mn0 + rq);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * 256;
+      const int idx = tid + v * NT;
       if constexpr (KCONTIG) {
         const int r = idx / (BK / 4);
         const int kq = (idx % (BK / 4)) * 4;
         const int gm = mn0 + r, gk = k0 + kq;
-        if (vec_ok && gm < mn_lim && gk + 3 < k_lim) {
-          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gm * ld + gk);
-        } else {
-          const bool rok = gm < mn_lim;
-          const float* p = X + (int64_t)(rok ? gm : 0) * ld;
-          reg[v].x = (rok && gk + 0 < k_lim) ? p[gk + 0] : 0.f;
-          reg[v].y = (rok && gk + 1 < k_lim) ? p[gk + 1] : 0.f;
-          reg[v].z = (rok && gk + 2 < k_lim) ? p[gk + 2] : 0.f;
-          reg[v].w = (rok && gk + 3 < k_lim) ? p[gk + 3] : 0.f;
-        }
+        const bool rok = gm < mn_lim;
+        const float* p = X + (int64_t)(rok ? gm : 0) * ld;
+        reg[v].x = (rok && gk + 0 < k_lim) ? p[gk + 0] : 0.f;
+        reg[v].y = (rok && gk + 1 < k_lim) ? p[gk + 1] : 0.f;
+        reg[v].z = (rok && gk + 2 < k_lim) ? p[gk + 2] : 0.f;
+        reg[v].w = (rok && gk + 3 < k_lim) ? p[gk + 3] : 0.f;
       } else {
         const int k = idx / (R / 4);
         const int rq = (idx % (R / 4)) * 4;
         const int gk = k0 + k, gm = mn0 + rq;
-        if (vec_ok && gk < k_lim && gm + 3 < mn_lim) {
-          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gk * ld + gm);
-        } else {
-          const bool kok = gk < k_lim;
-          const float* p = X + (int64_t)(kok ? gk : 0) * ld;
-          reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : 0.f;
-          reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : 0.f;
-          reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : 0.f;
-          reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : 0.f;
-        }
+        const bool kok = gk < k_lim;
+        const float* p = X + (int64_t)(kok ? gk : 0) * ld;
+        const float one = kok ? 1.f : 0.f;
+        reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : (gm + 0 == ones_col ? one : 0.f);
+        reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : (gm + 1 == ones_col ? one : 0.f);
+        reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : (gm + 2 == ones_col ? one : 0.f);
+        reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : (gm + 3 == ones_col ? one : 0.f);
       }
     }
   }
@@ -99,7 +131,7 @@ struct Tile {
   __device__ inline void store(float* __restrict__ Xs, int tid) const {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * 256;
+      const int idx = tid + v * NT;
       if constexpr (KCONTIG) {
         const int r = idx / (BK / 4);
         const int kq = (idx % (BK / 4)) * 4;
@@ -116,14 +148,30 @@ struct Tile {
   }
 };
 
+// C[row, col] = mask(relu(v + beta C)) and optionally sigmoid(C) into sig_out.
+__device__ inline void epilogue_store(const ProbDev& P, int row, int col, float v) {
+  float* cp = P.C + (int64_t)row * P.ldc + col;
+  if (P.beta != 0.f) v += P.beta * *cp;
+  if (P.relu) v = fmaxf(v, 0.f);
+  if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
+  *cp = v;
+  if (P.sig_out) {
+    const float e = expf(-fabsf(v));
+    const float r = 1.0f / (1.0f + e);
+    P.sig_out[(int64_t)row * P.ld_sig + col] = v >= 0.0f ? r : e * r;
+  }
+}
+
 // A_T: A stored [K, M] (M contiguous); otherwise [M, K].
 // B_T: B stored [N, K] (K contiguous); otherwise [K, N].
-template <int BM, int BN, bool A_T, bool B_T>
-__global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
-  constexpr int TM = BM / 64;  // 32x32 tiles per wave along M
-  constexpr int TN = BN / 64;
-  using TA = Tile<BM, !A_T>;
-  using TB = Tile<BN, B_T>;
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / (32 * WM);  // 32x32 accumulators per wave along M
+  constexpr int TN = BN / (32 * WN);
+  static_assert(TM >= 1 && TN >= 1 && TM * 32 * WM == BM && TN * 32 * WN == BN, "bad tiling");
+  using TA = Tile<BM, BK, NT, !A_T>;
+  using TB = Tile<BN, BK, NT, B_T>;
   __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
   __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
 
@@ -144,7 +192,7 @@ __global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int half = lane >> 5, l32 = lane & 31;
 
   const int nt0 = (P.K[0] + BK - 1) / BK;
@@ -164,11 +212,13 @@ __global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
 
   TA ta;
   TB tb;
+  const int ones_col = P.bias_grad ? P.N : -1;
   auto load = [&](int kt) {
     const int pc = kt < nt0 ? 0 : 1;
     const int k0 = (kt - (pc ? nt0 : 0)) * BK;
-    ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid);
-    tb.load(P.B[pc], P.ldb[pc], n0, P.N, k0, P.K[pc], P.vecB[pc] != 0, tid);
+    ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid, -1);
+    tb.load(P.B[pc], P.ldb[pc], n0, P.N, k0, P.K[pc], P.vecB[pc] != 0 && ones_col < 0, tid,
+            ones_col);
   };
 
   if (kt_begin < kt_end) {
@@ -182,20 +232,22 @@ __global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
       if (more) load(kt + 1);
       const float* as = As[cur];
       const float* bs = Bs[cur];
+      float af[BK / 2][TM], bf[BK / 2][TN];
 #pragma unroll
       for (int kk = 0; kk < BK / 2; ++kk) {
         const int kr = 2 * kk + half;
-        float a[TM], b[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
+        for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
+        for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK / 2; ++kk)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
       if (more) {
         ta.store(As[cur ^ 1], tid);
         tb.store(Bs[cur ^ 1], tid);
@@ -207,28 +259,26 @@ __global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
   // Accumulator layout of the 32x32 MFMA: register r of lane l holds
   // D[8*(r/4) + 4*(l/32) + r%4][l%32].
   const bool partial = args.splits > 1;
-  float* part = partial ? args.partial + P.part_off + (int64_t)split * P.M * P.N : nullptr;
+  float* part = partial ? args.partial + P.part_off + (int64_t)split * P.M * P.n_eff : nullptr;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int col = n0 + (wn * TN + j) * 32 + l32;
-      if (col >= P.N) continue;
-      const float bv = (!partial && P.bias) ? P.bias[col] : 0.f;
+      if (col >= P.n_eff) continue;
+      const bool virt = col == P.N;  // the bias-gradient column
+      const float bv = (!partial && !virt && P.bias) ? P.bias[col] : 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + (wm * TM + i) * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
         if (row >= P.M) continue;
-        float v = acc[i][j][r];
+        const float v = acc[i][j][r];
         if (partial) {
-          part[(int64_t)row * P.N + col] = v;
+          part[(int64_t)row * P.n_eff + col] = v;
+        } else if (virt) {
+          P.bias_grad[row] = v;
         } else {
-          float* cp = P.C + (int64_t)row * P.ldc + col;
-          if (P.beta != 0.f) v += P.beta * *cp;
-          v += bv;
-          if (P.relu) v = fmaxf(v, 0.f);
-          if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
-          *cp = v;
+          epilogue_store(P, row, col, v + bv);
         }
       }
     }
@@ -239,132 +289,174 @@ __global__ __launch_bounds__(256) void k_gemm(LaunchArgs args) {
 __global__ void k_gemm_splitk_reduce(LaunchArgs args) {
   const int prob = blockIdx.y;
   const ProbDev& P = args.p[prob];
-  const int64_t total = (int64_t)P.M * P.N;
+  const int64_t total = (int64_t)P.M * P.n_eff;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const float* part = args.partial + P.part_off;
   float v = 0.f;
   for (int s = 0; s < args.splits; ++s) v += part[(int64_t)s * total + idx];
-  const int row = (int)(idx / P.N);
-  const int col = (int)(idx - (int64_t)row * P.N);
-  float* cp = P.C + (int64_t)row * P.ldc + col;
-  if (P.beta != 0.f) v += P.beta * *cp;
+  const int row = (int)(idx / P.n_eff);
+  const int col = (int)(idx - (int64_t)row * P.n_eff);
+  if (col == P.N) {
+    P.bias_grad[row] = v;
+    return;
+  }
   if (P.bias) v += P.bias[col];
-  if (P.relu) v = fmaxf(v, 0.f);
-  if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
-  *cp = v;
+  epilogue_store(P, row, col, v);
 }
 
 inline bool vec_ok(const float* p, int64_t ld) {
   return (reinterpret_cast<uintptr_t>(p) % 16 == 0) && (ld % 4 == 0);
 }
 
+// ---- configurations -------------------------------------------------------
+struct Cfg {
+  int bm, bn, bk, wm, wn;
+};
+constexpr Cfg kCfgs[] = {
+    {64, 64, 32, 2, 2},    // 0: 256 threads, one 32x32 accumulator per wave
+    {64, 64, 32, 2, 1},    // 1: 128 threads, 32x64 per wave
+    {64, 64, 32, 1, 1},    // 2: 64 threads, 64x64 per wave
+    {128, 64, 32, 2, 2},   // 3: 256 threads, 64x32 per wave
+    {64, 128, 32, 2, 2},   // 4: 256 threads, 32x64 per wave
+    {128, 128, 32, 2, 2},  // 5: 256 threads, 64x64 per wave
+    {64, 64, 16, 2, 2},    // 6
+    {128, 128, 16, 2, 2},  // 7
+    {32, 64, 32, 1, 1},    // 8: 64 threads, 32x64 per wave
+    {64, 32, 32, 1, 1},    // 9: 64 threads, 64x32 per wave
+};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+const char* kCfgNames[kNumCfgs] = {"64x64x32_w2x2",   "64x64x32_w2x1", "64x64x32_w1x1",
+                                   "128x64x32_w2x2",  "64x128x32_w2x2", "128x128x32_w2x2",
+                                   "64x64x16_w2x2",   "128x128x16_w2x2", "32x64x32_w1x1",
+                                   "64x32x32_w1x1"};
+
 struct Plan {
-  int bm, bn, splits;
+  int cfg, splits;
 };
 
-int total_k_tiles(const GemmProblem& q) {
-  int kt = (int)ceil_div(q.piece[0].K, BK);
-  if (q.n_pieces > 1) kt += (int)ceil_div(q.piece[1].K, BK);
+inline int n_eff_of(const GemmProblem& q) { return q.N + (q.bias_grad ? 1 : 0); }
+
+int total_k_tiles(const GemmProblem& q, int bk) {
+  int kt = (int)ceil_div(q.piece[0].K, bk);
+  if (q.n_pieces > 1) kt += (int)ceil_div(q.piece[1].K, bk);
   return kt;
 }
 
-// Tile shape and split count: fill at least ~2 waves of 256 CUs.
-Plan choose_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, bool can_split) {
-  (void)a_t;
-  (void)b_t;
-  int64_t tiles64 = 0, tiles128 = 0;
-  int max_kt = 0;
-  for (int i = 0; i < n; ++i) {
-    tiles64 += ceil_div(probs[i].M, 64) * ceil_div(probs[i].N, 64);
-    tiles128 += ceil_div(probs[i].M, 128) * ceil_div(probs[i].N, 128);
-    max_kt = max(max_kt, total_k_tiles(probs[i]));
-  }
-  Plan p{64, 64, 1};
-  if (tiles128 >= 1024) { p.bm = 128; p.bn = 128; }
-  int64_t tiles = (p.bm == 128) ? tiles128 : tiles64;
-  if (can_split && tiles < 512 && max_kt >= 16) {
-    int s = (int)ceil_div(512, tiles);
-    s = min(s, max(1, max_kt / 8));  // keep >= 8 K tiles per split
-    p.splits = max(1, min(s, 64));
-  }
+int64_t tiles_of(const GemmProblem* probs, int n, const Cfg& c) {
+  int64_t t = 0;
+  for (int i = 0; i < n; ++i) t += ceil_div(probs[i].M, c.bm) * ceil_div(n_eff_of(probs[i]), c.bn);
+  return t;
+}
+
+int max_k_tiles(const GemmProblem* probs, int n, int bk) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) m = max(m, total_k_tiles(probs[i], bk));
+  return m;
+}
+
+// Split count that brings the launch to ~512 blocks, keeping >= 4 K steps per split.
+int heuristic_splits(const GemmProblem* probs, int n, const Cfg& c) {
+  const int64_t tiles = tiles_of(probs, n, c);
+  const int mkt = max_k_tiles(probs, n, c.bk);
+  if (tiles >= 512 || mkt < 8) return 1;
+  int s = (int)ceil_div(512, tiles);
+  s = min(s, max(1, mkt / 4));
+  return max(1, min(s, 64));
+}
+
+Plan heuristic_plan(const GemmProblem* probs, int n, bool can_split) {
+  Plan p{0, 1};
+  if (tiles_of(probs, n, kCfgs[5]) >= 1024) p.cfg = 5;
+  if (can_split) p.splits = heuristic_splits(probs, n, kCfgs[p.cfg]);
   return p;
 }
 
-size_t partial_floats(const Plan& pl, const GemmProblem* probs, int n) {
-  if (pl.splits <= 1) return 0;
+size_t partial_floats(int splits, const GemmProblem* probs, int n) {
+  if (splits <= 1) return 0;
   size_t f = 0;
-  for (int i = 0; i < n; ++i) f += (size_t)pl.splits * probs[i].M * probs[i].N;
+  for (int i = 0; i < n; ++i) f += (size_t)splits * probs[i].M * n_eff_of(probs[i]);
   return f;
 }
 
-template <bool A_T, bool B_T>
-cpra_status launch(const Plan& pl, LaunchArgs& args, hipStream_t stream) {
+// ---- tuning table -----------------------------------------------------------
+struct TuneEntry {
+  Plan plan;
+  double us;
+  double heuristic_us;
+};
+
+std::mutex g_tune_mu;
+bool g_tuning = false;
+std::map<std::string, TuneEntry> g_table;
+std::vector<std::string> g_order;
+
+std::string shape_key(bool a_t, bool b_t, const GemmProblem* probs, int n) {
+  std::string k = a_t ? "T" : "N";
+  k += b_t ? "T" : "N";
+  char buf[96];
+  for (int i = 0; i < n; ++i) {
+    const GemmProblem& q = probs[i];
+    snprintf(buf, sizeof(buf), "|%dx%dx%d", q.M, n_eff_of(q),
+             q.piece[0].K + (q.n_pieces > 1 ? q.piece[1].K : 0));
+    k += buf;
+  }
+  return k;
+}
+
+bool lookup(const std::string& key, Plan* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_table.find(key);
+  if (it == g_table.end()) return false;
+  *out = it->second.plan;
+  return true;
+}
+
+// ---- launching ---------------------------------------------------------------
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T>
+void launch_cfg(LaunchArgs& args, hipStream_t stream) {
   int max_tiles = 0;
   for (int i = 0; i < args.n_prob; ++i) {
-    args.p[i].tiles_m = (int)ceil_div(args.p[i].M, pl.bm);
-    args.p[i].tiles_n = (int)ceil_div(args.p[i].N, pl.bn);
+    args.p[i].tiles_m = (int)ceil_div(args.p[i].M, BM);
+    args.p[i].tiles_n = (int)ceil_div(args.p[i].n_eff, BN);
     max_tiles = max(max_tiles, args.p[i].tiles_m * args.p[i].tiles_n);
   }
   args.grid_x = (int)ceil_div(max_tiles, 8) * 8;
   dim3 grid(args.grid_x, args.n_prob * args.splits);
-  double flops = 0, red_bytes = 0;
-  for (int i = 0; i < args.n_prob; ++i) {
-    const double mn = (double)args.p[i].M * args.p[i].N;
-    flops += 2.0 * mn * ((double)args.p[i].K[0] + (args.p[i].n_pieces > 1 ? args.p[i].K[1] : 0));
-    red_bytes += 4.0 * mn * (args.splits + 1);
-  }
-  static const char* names[2][2][2] = {
-      {{"gemm_nn_64x64", "gemm_nt_64x64"}, {"gemm_tn_64x64", "gemm_tt_64x64"}},
-      {{"gemm_nn_128x128", "gemm_nt_128x128"}, {"gemm_tn_128x128", "gemm_tt_128x128"}}};
-  {
-    ProfScope ps(names[pl.bm == 128][A_T][B_T], stream, flops, 0.0);
-    if (pl.bm == 128)
-      hipLaunchKernelGGL((k_gemm<128, 128, A_T, B_T>), grid, dim3(256), 0, stream, args);
-    else
-      hipLaunchKernelGGL((k_gemm<64, 64, A_T, B_T>), grid, dim3(256), 0, stream, args);
-  }
-  CPRA_CHECK_LAUNCH("gemm");
-  if (args.splits > 1) {
-    int64_t maxel = 0;
-    for (int i = 0; i < args.n_prob; ++i) maxel = max(maxel, (int64_t)args.p[i].M * args.p[i].N);
-    {
-      ProfScope ps("gemm_splitk_reduce", stream, 0.0, red_bytes);
-      hipLaunchKernelGGL(k_gemm_splitk_reduce, dim3(ceil_div(maxel, 256), args.n_prob), dim3(256), 0,
-                         stream, args);
-    }
-    CPRA_CHECK_LAUNCH("gemm_splitk_reduce");
-  }
-  return CPRA_OK;
+  hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T>), grid, dim3(64 * WM * WN), 0, stream,
+                     args);
 }
 
-}  // namespace
-
-size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, int n) {
-  Plan pl = choose_plan(a_t, b_t, probs, n, true);
-  return partial_floats(pl, probs, n) * sizeof(float);
+template <bool A_T, bool B_T>
+void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
+  switch (cfg) {
+#define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN) \
+  case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T>(args, stream); break;
+    CPRA_GEMM_CFG(0, 64, 64, 32, 2, 2)
+    CPRA_GEMM_CFG(1, 64, 64, 32, 2, 1)
+    CPRA_GEMM_CFG(2, 64, 64, 32, 1, 1)
+    CPRA_GEMM_CFG(3, 128, 64, 32, 2, 2)
+    CPRA_GEMM_CFG(4, 64, 128, 32, 2, 2)
+    CPRA_GEMM_CFG(5, 128, 128, 32, 2, 2)
+    CPRA_GEMM_CFG(6, 64, 64, 16, 2, 2)
+    CPRA_GEMM_CFG(7, 128, 128, 16, 2, 2)
+    CPRA_GEMM_CFG(8, 32, 64, 32, 1, 1)
+    CPRA_GEMM_CFG(9, 64, 32, 32, 1, 1)
+#undef CPRA_GEMM_CFG
+    default: break;
+  }
 }
 
-cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws,
-                       size_t ws_bytes, hipStream_t stream) {
-  if (n < 1 || n > kMaxProblems) CPRA_FAIL(CPRA_ERR_PARAM, "gemm: 1..4 problems per launch");
-  int live = 0;
-  for (int i = 0; i < n; ++i)
-    if (probs[i].M > 0 && probs[i].N > 0) ++live;
-  if (live == 0) return CPRA_OK;
-  // Without a workspace the contraction is not split (correct, possibly slower).
-  Plan pl = choose_plan(a_t, b_t, probs, n, ws != nullptr && ws_bytes > 0);
-  size_t need = partial_floats(pl, probs, n) * sizeof(float);
-  if (need > 0 && (ws == nullptr || ws_bytes < need))
-    CPRA_FAIL(CPRA_ERR_WORKSPACE, "gemm: workspace %zu < %zu bytes", ws_bytes, need);
-  LaunchArgs args{};
-  args.n_prob = n;
-  args.splits = pl.splits;
-  args.partial = static_cast<float*>(ws);
+void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs* args) {
+  *args = LaunchArgs{};
+  args->n_prob = n;
+  args->splits = splits;
+  args->partial = static_cast<float*>(ws);
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     const GemmProblem& q = probs[i];
-    ProbDev& d = args.p[i];
+    ProbDev& d = args->p[i];
     d.n_pieces = q.n_pieces;
     for (int pc = 0; pc < 2; ++pc) {
       const GemmPiece& g = q.piece[pc < q.n_pieces ? pc : 0];
@@ -385,13 +477,144 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void
     d.ld_mask = q.ld_mask;
     d.beta = q.beta;
     d.relu = q.relu;
+    d.bias_grad = q.bias_grad;
+    d.sig_out = q.sig_out;
+    d.ld_sig = q.ld_sig;
+    d.n_eff = n_eff_of(q);
     d.part_off = off;
-    off += (int64_t)pl.splits * q.M * q.N;
+    off += (int64_t)splits * q.M * d.n_eff;
   }
-  if (!a_t && b_t) return launch<false, true>(pl, args, stream);
-  if (!a_t && !b_t) return launch<false, false>(pl, args, stream);
-  if (a_t && !b_t) return launch<true, false>(pl, args, stream);
-  return launch<true, true>(pl, args, stream);
+}
+
+cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const Plan& pl, void* ws,
+                     hipStream_t stream) {
+  LaunchArgs args;
+  fill_args(probs, n, pl.splits, ws, &args);
+  double flops = 0, red_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    const double mn = (double)args.p[i].M * args.p[i].n_eff;
+    flops += 2.0 * mn * ((double)args.p[i].K[0] + (args.p[i].n_pieces > 1 ? args.p[i].K[1] : 0));
+    red_bytes += 4.0 * mn * (pl.splits + 1);
+  }
+  static const char* layout[2][2] = {{"gemm_nn", "gemm_nt"}, {"gemm_tn", "gemm_tt"}};
+  {
+    ProfScope ps(layout[a_t][b_t], stream, flops, 0.0);
+    if (!a_t && b_t) launch_any<false, true>(pl.cfg, args, stream);
+    else if (!a_t && !b_t) launch_any<false, false>(pl.cfg, args, stream);
+    else if (a_t && !b_t) launch_any<true, false>(pl.cfg, args, stream);
+    else launch_any<true, true>(pl.cfg, args, stream);
+  }
+  CPRA_CHECK_LAUNCH("gemm");
+  if (pl.splits > 1) {
+    int64_t maxel = 0;
+    for (int i = 0; i < n; ++i) maxel = max(maxel, (int64_t)args.p[i].M * args.p[i].n_eff);
+    {
+      ProfScope ps("gemm_splitk_reduce", stream, 0.0, red_bytes);
+      hipLaunchKernelGGL(k_gemm_splitk_reduce, dim3(ceil_div(maxel, 256), n), dim3(256), 0, stream,
+                         args);
+    }
+    CPRA_CHECK_LAUNCH("gemm_splitk_reduce");
+  }
+  return CPRA_OK;
+}
+
+// Time every candidate (tile config x split count that fits the workspace) and
+// keep the fastest.  Runs on `stream`, synchronising it; the candidates all
+// compute the same C (overwritten each time), so re-running the chosen plan
+// leaves its result.
+cpra_status tune(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws, size_t ws_bytes,
+                 hipStream_t stream, const std::string& key, Plan* best_out) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    CPRA_FAIL(CPRA_ERR_HIP, "gemm tune: event creation failed");
+  const Plan heur = heuristic_plan(probs, n, ws != nullptr);
+  const char* env = getenv("CPRA_AUTOTUNE_LOG");  // print every candidate's time
+  const bool log_candidates = env != nullptr && env[0] == '1';
+  TuneEntry entry{Plan{0, 1}, 1e30, -1.0};
+  for (int c = 0; c < kNumCfgs; ++c) {
+    std::vector<int> splits = {1};
+    const int h = heuristic_splits(probs, n, kCfgs[c]);
+    if (ws != nullptr && h > 1) {
+      for (int s : {h / 2, h, 2 * h})
+        if (s > 1 && s <= 64 && partial_floats(s, probs, n) * sizeof(float) <= ws_bytes &&
+            s != splits.back())
+          splits.push_back(s);
+    }
+    for (int s : splits) {
+      Plan pl{c, s};
+      CPRA_CHECK(run_plan(a_t, b_t, probs, n, pl, ws, stream));  // warm-up
+      hipEventRecord(e0, stream);
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) CPRA_CHECK(run_plan(a_t, b_t, probs, n, pl, ws, stream));
+      hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "gemm tune: sync failed");
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1e3 * ms / reps;
+      if (log_candidates)
+        fprintf(stderr, "[cpra autotune] %s %s/split%d %.2f us\n", key.c_str(), kCfgNames[c], s, us);
+      if (c == heur.cfg && s == heur.splits) entry.heuristic_us = us;
+      if (us < entry.us) {
+        entry.us = us;
+        entry.plan = pl;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_table.find(key) == g_table.end()) g_order.push_back(key);
+    g_table[key] = entry;
+  }
+  *best_out = entry.plan;
+  return run_plan(a_t, b_t, probs, n, entry.plan, ws, stream);
+}
+
+}  // namespace
+
+size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, int n) {
+  (void)a_t;
+  (void)b_t;
+  // Room for any candidate the tuner may pick: twice the heuristic split of any config.
+  size_t best = 0;
+  for (int c = 0; c < kNumCfgs; ++c) {
+    const int h = heuristic_splits(probs, n, kCfgs[c]);
+    const int s = h > 1 ? min(64, 2 * h) : 1;
+    if (s > 1) best = std::max(best, partial_floats(s, probs, n) * sizeof(float));
+  }
+  return best;
+}
+
+cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (n < 1 || n > kMaxProblems) CPRA_FAIL(CPRA_ERR_PARAM, "gemm: 1..4 problems per launch");
+  for (int i = 0; i < n; ++i)
+    if (probs[i].bias_grad && (b_t || probs[i].bias))
+      CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad needs B stored [K, N] and no bias");
+  int live = 0;
+  for (int i = 0; i < n; ++i)
+    if (probs[i].M > 0 && n_eff_of(probs[i]) > 0) ++live;
+  if (live == 0) return CPRA_OK;
+  const bool can_split = ws != nullptr && ws_bytes > 0;
+  const std::string key = shape_key(a_t, b_t, probs, n);
+  Plan pl;
+  if (!lookup(key, &pl)) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing =
+        hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    bool overwrite_only = true;  // tuning re-runs the GEMM: only if C is overwritten
+    for (int i = 0; i < n; ++i) overwrite_only = overwrite_only && probs[i].beta == 0.f;
+    if (g_tuning && !capturing && overwrite_only)
+      return tune(a_t, b_t, probs, n, can_split ? ws : nullptr, can_split ? ws_bytes : 0, stream,
+                  key, &pl);
+    pl = heuristic_plan(probs, n, can_split);
+  }
+  // A tuned plan may split more than this workspace allows: fall back to fewer splits.
+  if (!can_split) pl.splits = 1;
+  while (pl.splits > 1 && partial_floats(pl.splits, probs, n) * sizeof(float) > ws_bytes)
+    pl.splits /= 2;
+  return run_plan(a_t, b_t, probs, n, pl, ws, stream);
 }
 
 }  // namespace cpra
@@ -439,6 +662,41 @@ cpra_status cpra_gemm(int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, c
   cpra::GemmProblem q;
   CPRA_CHECK(make_problem(ta, tb, M, N, K, A, lda, B, ldb, beta, C, ldc, bias, relu, &q));
   return cpra::gemm_batch(ta != 0, tb != 0, &q, 1, ws, ws_bytes, cpra::as_stream(stream));
+}
+
+cpra_status cpra_autotune_begin(void) {
+  std::lock_guard<std::mutex> lk(cpra::g_tune_mu);
+  cpra::g_tuning = true;
+  return CPRA_OK;
+}
+
+cpra_status cpra_autotune_end(int32_t* n_entries) {
+  std::lock_guard<std::mutex> lk(cpra::g_tune_mu);
+  cpra::g_tuning = false;
+  if (n_entries) *n_entries = (int32_t)cpra::g_order.size();
+  return CPRA_OK;
+}
+
+cpra_status cpra_autotune_reset(void) {
+  std::lock_guard<std::mutex> lk(cpra::g_tune_mu);
+  cpra::g_table.clear();
+  cpra::g_order.clear();
+  return CPRA_OK;
+}
+
+cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, char* choice,
+                              size_t choice_len, double* us, double* heuristic_us) {
+  using namespace cpra;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (i < 0 || i >= (int32_t)g_order.size())
+    CPRA_FAIL(CPRA_ERR_PARAM, "autotune_get: index out of range");
+  const TuneEntry& e = g_table[g_order[i]];
+  if (key && key_len) snprintf(key, key_len, "%s", g_order[i].c_str());
+  if (choice && choice_len)
+    snprintf(choice, choice_len, "%s/split%d", kCfgNames[e.plan.cfg], e.plan.splits);
+  if (us) *us = e.us;
+  if (heuristic_us) *heuristic_us = e.heuristic_us;
+  return CPRA_OK;
 }
 
 }  // extern "C"

@@ -157,58 +157,6 @@ cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t
   return CPRA_OK;
 }
 
-// Column sums in two fixed-order stages: (1) block (cx, sy) sums rows of split sy
-// for 64 columns with 4 row-lanes; (2) sum the splits in order.
-static constexpr int kColsumRowsPerSplit = 1024;
-
-__global__ void k_colsum_partial(int M, int N, const float* __restrict__ X, int64_t ldx,
-                                 float* __restrict__ part) {
-  int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  int rl = threadIdx.x >> 6;  // 0..3
-  int r0 = blockIdx.y * kColsumRowsPerSplit;
-  int r1 = min(M, r0 + kColsumRowsPerSplit);
-  float acc = 0.0f;
-  if (c < N)
-    for (int r = r0 + rl; r < r1; r += 4) acc += X[(int64_t)r * ldx + c];
-  __shared__ float sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  if (rl == 0 && c < N) {
-    float s = ((sh[threadIdx.x] + sh[threadIdx.x + 64]) + sh[threadIdx.x + 128]) + sh[threadIdx.x + 192];
-    part[(int64_t)blockIdx.y * N + c] = s;
-  }
-}
-
-__global__ void k_colsum_final(int N, int nsplit, const float* __restrict__ part, float* __restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  double acc = 0.0;
-  for (int s = 0; s < nsplit; ++s) acc += (double)part[(int64_t)s * N + c];
-  out[c] = (float)acc;
-}
-
-size_t colsum_workspace_bytes(int M, int N) {
-  return (size_t)ceil_div(M, kColsumRowsPerSplit) * (size_t)N * sizeof(float);
-}
-
-cpra_status colsum(int M, int N, const float* X, int64_t ldx, float* out, void* ws,
-                   size_t ws_bytes, hipStream_t stream) {
-  if (N <= 0) return CPRA_OK;
-  int nsplit = (int)ceil_div(M, kColsumRowsPerSplit);
-  if (nsplit == 0) nsplit = 1;
-  if (ws_bytes < (size_t)nsplit * N * sizeof(float))
-    CPRA_FAIL(CPRA_ERR_WORKSPACE, "colsum: workspace too small");
-  float* part = static_cast<float*>(ws);
-  ProfScope ps("colsum", stream, 0.0, 4.0 * ((double)M * N + 2.0 * nsplit * N));
-  hipLaunchKernelGGL(k_colsum_partial, dim3(ceil_div(N, 64), nsplit), dim3(256), 0, stream, M, N, X,
-                     ldx, part);
-  CPRA_CHECK_LAUNCH("colsum_partial");
-  hipLaunchKernelGGL(k_colsum_final, dim3(ceil_div(N, 256)), dim3(256), 0, stream, N, nsplit, part,
-                     out);
-  CPRA_CHECK_LAUNCH("colsum_final");
-  return CPRA_OK;
-}
-
 }  // namespace cpra
 
 extern "C" {

@@ -13,7 +13,9 @@
 //    dH = G_s + M^T G_n (masked by H > 0 in the same pass);
 //  * linear-first: T = M^T dY, dWs = dY^T H, dWn = T^T H,
 //    dH = [dY | T] [Ws; Wn] (masked in the GEMM epilogue).
-// db = column sums of dY.  M^T = A D^-1 is applied by the transposed
+// db = column sums of dY, produced by the dWs GEMM through a virtual ones
+// column (no separate pass).  The output layer also writes P = sigmoid(Z) in
+// its epilogue, for the loss.  M^T = A D^-1 is applied by the transposed
 // aggregation (not M: the graph need not be regular).  With recompute set,
 // AX is not kept from the forward and is rebuilt in the backward.
 #include <algorithm>
@@ -44,8 +46,8 @@ struct Plan {
   size_t h_off[kMaxLayers];   // saved input of layer k (k >= 1)
   size_t ax_off[kMaxLayers];  // saved M H of aggregate-first layers
   size_t ax_scratch_off;      // recompute buffer
-  size_t yy_off, d_off[2], g_off, t_off, gemm_off, colsum_off;
-  size_t gemm_bytes, colsum_bytes;
+  size_t yy_off, d_off[2], g_off, t_off, p_off, gemm_off;
+  size_t gemm_bytes;
   size_t total;
 };
 
@@ -99,6 +101,7 @@ void wgrad_problems(const Plan& p, int k, GemmProblem* q) {
     q[i].M = l.out;
     q[i].N = l.in;
   }
+  if (p.sage) q[0].bias_grad = reinterpret_cast<float*>(1);  // shape only: one extra column
 }
 
 void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
@@ -129,17 +132,15 @@ void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
   p->d_off[1] = max_in_after0 ? take((size_t)N * max_in_after0 * f) : 0;
   p->g_off = max_in_af ? take((size_t)N * 2 * max_in_af * f) : 0;
   p->t_off = max_out_lf ? take((size_t)N * max_out_lf * f) : 0;
-  size_t gb = 0, cb = 0;
+  p->p_off = take((size_t)N * cfg->S * f);
+  size_t gb = 0;
   for (int k = 0; k < p->L; ++k) {
     GemmProblem q[2];
     wgrad_problems(*p, k, q);
     gb = std::max(gb, gemm_batch_workspace_bytes(true, false, q, 2));
-    cb = std::max(cb, colsum_workspace_bytes(N, p->layer[k].out));
   }
   p->gemm_bytes = gb;
-  p->colsum_bytes = cb;
   p->gemm_off = gb ? take(gb) : 0;
-  p->colsum_off = cb ? take(cb) : 0;
   p->total = std::max<size_t>(off, 256);
 }
 
@@ -160,6 +161,7 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
     const float* Ws = params + l.off_ws;
     const float* Wn = params + l.off_wn;
     const float* b = p.sage ? params + l.off_b : nullptr;
+    float* P = last ? fptr(ws, p.p_off) : nullptr;  // sigmoid(Z) for the loss
     if (!l.lf) {
       float* AX = fptr(ws, p.recompute ? p.ax_scratch_off : p.ax_off[k]);
       CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
@@ -173,6 +175,8 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       q.N = l.out;
       q.bias = b;
       q.relu = last ? 0 : 1;
+      q.sig_out = P;
+      q.ld_sig = l.out;
       CPRA_CHECK(gemm_batch(false, true, &q, 1, nullptr, 0, st));
     } else {
       float* YY = fptr(ws, p.yy_off);
@@ -188,7 +192,7 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       }
       CPRA_CHECK(gemm_batch(false, true, q, 2, nullptr, 0, st));
       CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, b, !last, nullptr,
-                           0, st));
+                           0, st, P, l.out));
     }
     H = dst;
     ldh = ldd;
@@ -203,7 +207,6 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
   int64_t lddy = lddz;
   int ping = 0;
   void* gemm_ws = p.gemm_bytes ? static_cast<char*>(ws) + p.gemm_off : nullptr;
-  void* col_ws = p.colsum_bytes ? static_cast<char*>(ws) + p.colsum_off : nullptr;
   for (int k = p.L - 1; k >= 0; --k) {
     const Layer& l = p.layer[k];
     const float* Hk = (k == 0) ? params : fptr(ws, p.h_off[k]);
@@ -215,8 +218,6 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
     float* dX = (k == 0) ? grads : fptr(ws, p.d_off[ping]);
     const int64_t lddx = l.in;
     const float* mask = (k == 0) ? nullptr : Hk;  // H_k = ReLU output of layer k-1
-    if (p.sage)
-      CPRA_CHECK(colsum(N, l.out, dY, lddy, grads + l.off_b, col_ws, p.colsum_bytes, st));
     if (l.lf) {
       float* T = fptr(ws, p.t_off);
       CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
@@ -229,6 +230,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].M = l.out;
         q[i].N = l.in;
       }
+      if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
       GemmProblem r{};
       r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
@@ -259,6 +261,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].M = l.out;
         q[i].N = l.in;
       }
+      if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
       float* G = fptr(ws, p.g_off);
       const int64_t ldg = 2 * l.in;
@@ -356,7 +359,7 @@ size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* c
   if (g == nullptr || cfg == nullptr || cpra::check_model_cfg(&cfg->model) != CPRA_OK) return 0;
   cpra::Plan p{};
   cpra::make_plan(&cfg->model, g->n_nodes, &p);
-  return cpra::align_up(p.total, 256) + cpra::loss_workspace_bytes(g, cfg->model.S, true);
+  return cpra::align_up(p.total, 256) + cpra::loss_workspace_bytes(g, cfg->model.S, false);
 }
 
 cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* params,
@@ -379,13 +382,13 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   Plan p{};
   make_plan(&cfg->model, g->n_nodes, &p);
   const size_t model_bytes = align_up(p.total, 256);
-  const size_t need = model_bytes + loss_workspace_bytes(g, cfg->model.S, true);
+  const size_t need = model_bytes + loss_workspace_bytes(g, cfg->model.S, false);
   if (ws == nullptr || ws_bytes < need)
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "train_step: workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t st = as_stream(stream);
   const int S = cfg->model.S;
   CPRA_CHECK(forward_impl(g, p, params, Z, S, ws, st));
-  CPRA_CHECK(loss_fwd_bwd(g, &lc, Z, S, nullptr, 0, dZ, S, terms,
+  CPRA_CHECK(loss_fwd_bwd(g, &lc, Z, S, fptr(ws, p.p_off), S, dZ, S, terms,
                           static_cast<char*>(ws) + model_bytes, ws_bytes - model_bytes, st));
   CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st));
   CPRA_CHECK(adam_step(p.n_params, params, grads, m, v, &cfg->adam, t, step_counter, st));

@@ -129,9 +129,11 @@ class CPRASolver:
         return out
 
     def loss_workspace(self) -> torch.Tensor:
-        """The loss part of the step workspace (it follows the model part)."""
-        mb = api.model_workspace_bytes(self.graph, self.model_cfg)
-        return self.ws[(mb + 255) // 256 * 256:]
+        """A workspace for standalone loss calls (computes P itself), allocated once."""
+        if getattr(self, "_loss_ws", None) is None:
+            nb = api.loss_workspace_bytes(self.graph, self.loss_cfg)
+            self._loss_ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+        return self._loss_ws
 
     # -- training -----------------------------------------------------------
     def step(self, stream=None) -> None:
@@ -139,6 +141,18 @@ class CPRASolver:
         api.train_step(self.graph, self.step_cfg, self.params, self.grads, self.m, self.v, self.Z,
                        self.dZ, self.terms, self.ws, 1, self.step_counter, stream)
         self.t += 1
+
+    def autotune(self):
+        """One eager training step with the GEMM autotuner on (tile shapes and split
+        counts timed per problem shape); returns the tuning table.  The step is a real
+        training step: the device counter advances."""
+        api.autotune_begin()
+        try:
+            self.step()
+            torch.cuda.synchronize()
+        finally:
+            table = api.autotune_end()
+        return table
 
     def capture(self) -> None:
         """Record one training step into a HIP graph on a private stream."""

@@ -135,6 +135,38 @@ def test_gemm(ta, tb, shape):
     assert_close_array(Cd.cpu().numpy(), np.maximum(ref + 0.5 * C0 + bias, 0), 2e-6, "epilogue")
 
 
+def test_gemm_autotuned_plans_keep_parity():
+    a = api()
+    rng = np.random.default_rng(3)
+    shapes = [(False, True, 3000, 256, 512), (True, False, 256, 256, 5000), (False, False, 999, 100, 200)]
+    a.autotune_reset()
+    a.autotune_begin()
+    try:
+        for ta, tb, M, N, K in shapes:
+            A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+            B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+            C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+            a.gemm(to_dev(A), to_dev(B), C, ta, tb)
+            torch.cuda.synchronize()
+            ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
+            assert_close_array(C.cpu().numpy(), ref, 2e-6, f"tuning run {ta}{tb}")
+    finally:
+        table = a.autotune_end()
+    assert len(table) == len(shapes)
+    for key, choice, us, hus in table:
+        say(f"  tuned {key} -> {choice} {us:.1f} us (heuristic {hus:.1f} us)")
+        assert us > 0 and (hus < 0 or us <= hus * 1.0001)
+    for ta, tb, M, N, K in shapes:  # tuned plans in use, tuning off
+        A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+        B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+        C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+        a.gemm(to_dev(A), to_dev(B), C, ta, tb)
+        torch.cuda.synchronize()
+        ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
+        assert_close_array(C.cpu().numpy(), ref, 2e-6, f"tuned plan {ta}{tb}")
+    a.autotune_reset()
+
+
 def test_gemm_strided_and_unaligned_views():
     a = api()
     rng = np.random.default_rng(0)
