@@ -14,9 +14,10 @@ lambda_s = logspace(-1, 1, 100), alpha = 2, gamma -2 -> +0.1 over 5000
 steps, Adam lr 1e-3, FP32.  value = S * |E| / seconds per step.
 
 Besides the JSON line's throughput, the run measures per-kernel durations
-with HIP events (the library's profiler) over a second, eager timed region,
-reports the dominant kernel against its roofline, and times the FP64 CPU
-oracle on a bounded sample of the same workload.
+with HIP events (the library's profiler: an event pair around every kernel
+of eager steps queued behind a GPU sleep, so they run back to back), reports the dominant
+kernel against its roofline, and times the FP64 CPU oracle on a bounded
+sample of the same workload.
 """
 
 from __future__ import annotations
@@ -123,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning-file", default=None,
+                    help="GEMM tuning table: loaded if it exists, else written after autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its "
@@ -138,11 +141,20 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
 
-    # autotune the GEMM tile shapes on this workload's shapes (one real training step)
-    if not args.no_autotune:
+    # GEMM tile shapes: load a saved tuning table, or autotune on this workload's
+    # shapes (one real training step) and save the table
+    if args.tuning_file and os.path.exists(args.tuning_file):
+        with open(args.tuning_file) as f:
+            for e in json.load(f):
+                api.autotune_set(e["key"], e["cfg"], e["splits"])
+        log(f"[bench] loaded GEMM tuning table {args.tuning_file}")
+    elif not args.no_autotune:
         table = sol.autotune()
         for key, choice, us, hus in table:
             log(f"[bench] autotune {key:40s} -> {choice:26s} {us:8.2f} us (heuristic {hus:8.2f} us)")
+        if args.tuning_file:
+            with open(args.tuning_file, "w") as f:
+                json.dump(api.autotune_table(), f, indent=1)
     # warm-up: capture once, replay W steps
     sol.capture()
     sol.replay(args.warmup)
@@ -184,9 +196,16 @@ def main():
     }
 
     if not args.no_profile:
-        api.profile_begin()
-        for _ in range(args.profile_steps):
-            sol.step()
+        # per-kernel durations: eager steps with an event pair around every kernel,
+        # queued behind a GPU sleep so that the host runs ahead of the GPU and the
+        # kernels execute back to back as in the replayed graph
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            torch.cuda._sleep(int(2.4e9 * 0.004 * args.profile_steps))  # ~4 ms per step
+            api.profile_begin()
+            for _ in range(args.profile_steps):
+                sol.step(stream)
+            api.profile_stop()
         torch.cuda.synchronize()
         stats = api.profile_end()
         total = sum(v[1] for v in stats.values())

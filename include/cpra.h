@@ -227,9 +227,14 @@ cpra_status cpra_adam_step(int64_t n, float* params, const float* grads, float* 
 /* ------------------------------------------------------------------------
  * One full CPRA training step (Sec. 3.1 loop): forward, sigmoid, loss and
  * dZ, hand-written backward, Adam over all parameters (embedding included).
- * With step_counter non-NULL, gamma and Adam's t come from the device
- * counter and the step ends by incrementing it, so the same enqueued work
- * can be captured once and replayed for every step.
+ * With step_counter non-NULL (a device int32 holding the number of steps
+ * done, t - 1), gamma and Adam's t come from the device and the step
+ * increments the counter, so the same enqueued work can be captured once and
+ * replayed for every step.  The weight-gradient GEMMs and the loss-term
+ * reduction run on a library-owned second stream of the current device,
+ * forked from and joined back into `stream` by events (also when captured);
+ * CPRA_OVERLAP=0 in the environment keeps all work on `stream`.
+ * cpra_model_backward overlaps its weight gradients the same way.
  * ---------------------------------------------------------------------- */
 typedef struct {
   cpra_model_cfg model;
@@ -283,26 +288,35 @@ cpra_status cpra_graph_destroy(cpra_graph graph);
  * Tuning synchronises the stream; launches on a stream being captured and
  * GEMMs with beta != 0 are never tuned.  Later calls with a tuned shape use
  * the recorded plan, others a fixed heuristic.  autotune_get reads entry i:
- * the shape key, the chosen "config/splitN", its time and the time of the
- * heuristic plan (microseconds).
+ * the shape key, the chosen configuration index and split count, their name
+ * "config/splitN", its time and the time of the heuristic plan (microseconds).
  * ---------------------------------------------------------------------- */
 cpra_status cpra_autotune_begin(void);
 cpra_status cpra_autotune_end(int32_t* n_entries);
 cpra_status cpra_autotune_reset(void);
-cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, char* choice,
-                              size_t choice_len, double* us, double* heuristic_us);
+cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, int32_t* cfg, int32_t* splits,
+                              char* choice, size_t choice_len, double* us, double* heuristic_us);
+/* Insert or replace an entry (e.g. a table saved by an earlier run): shape key
+ * as returned by autotune_get, configuration index and split count. */
+cpra_status cpra_autotune_set(const char* key, int32_t cfg, int32_t splits);
 
 /* ------------------------------------------------------------------------
  * Per-kernel timing for roofline measurement.  Between profile_begin and
  * profile_end every kernel the library launches on a stream that is not
  * being captured is bracketed by two HIP events on that stream and tagged
  * with a kernel-family name and its algorithmic work (FLOPs for the GEMMs,
- * compulsory HBM bytes for the memory-bound kernels).  profile_end waits for
- * the recorded events and aggregates per family; profile_get reads family i:
+ * compulsory HBM bytes for the memory-bound kernels); launches on a stream
+ * being captured are not recorded.  profile_collect waits for the recorded
+ * events and adds their times to the per-family summary; profile_end frees
+ * the events and returns the number of families; profile_get reads family i:
  * launches, summed event time (ms), summed FLOPs and bytes.  Profiling adds
- * two event records per launch; it is meant for measurement runs only.
+ * two event records per launch: measurement runs only.  An event pair times
+ * the kernel plus any wait for the host to launch it, so keep the GPU queue
+ * ahead of the host (e.g. start with a sleep on the stream).
  * ---------------------------------------------------------------------- */
 cpra_status cpra_profile_begin(void);
+cpra_status cpra_profile_stop(void);     /* stop recording new launches, keep the events */
+cpra_status cpra_profile_collect(void);  /* add the recorded events' times to the summary */
 cpra_status cpra_profile_end(int32_t* n_kernels);
 cpra_status cpra_profile_get(int32_t i, char* name, size_t name_len, int64_t* launches,
                              double* total_ms, double* flops, double* bytes);

@@ -88,9 +88,12 @@ PROTOTYPES = {
     "cpra_autotune_begin": (None, []),
     "cpra_autotune_end": (None, [C.POINTER(I32)]),
     "cpra_autotune_reset": (None, []),
-    "cpra_autotune_get": (None, [I32, C.c_char_p, SZ, C.c_char_p, SZ, C.POINTER(C.c_double),
-                                 C.POINTER(C.c_double)]),
+    "cpra_autotune_get": (None, [I32, C.c_char_p, SZ, C.POINTER(I32), C.POINTER(I32), C.c_char_p,
+                                 SZ, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cpra_autotune_set": (None, [C.c_char_p, I32, I32]),
     "cpra_profile_begin": (None, []),
+    "cpra_profile_stop": (None, []),
+    "cpra_profile_collect": (None, []),
     "cpra_profile_end": (None, [C.POINTER(I32)]),
     "cpra_profile_get": (None, [I32, C.c_char_p, SZ, C.POINTER(I64), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),

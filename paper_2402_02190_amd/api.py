@@ -240,8 +240,19 @@ def profile_begin() -> None:
     call("cpra_profile_begin")
 
 
-def profile_end():
-    """Stop profiling; returns {name: (launches, total_ms, flops, bytes)}."""
+def profile_stop() -> None:
+    call("cpra_profile_stop")
+
+
+def profile_collect() -> None:
+    call("cpra_profile_collect")
+
+
+def profile_end(collect: bool = True):
+    """Stop profiling (collecting the recorded events first unless collect=False);
+    returns {name: (launches, total_ms, flops, bytes)}."""
+    if collect:
+        profile_collect()
     n = C.c_int32()
     call("cpra_profile_end", C.byref(n))
     out = {}
@@ -261,13 +272,29 @@ def autotune_end():
     """Stop tuning; returns [(shape key, chosen plan, us, heuristic us)] of the table."""
     n = C.c_int32()
     call("cpra_autotune_end", C.byref(n))
+    return [(e["key"], e["choice"], e["us"], e["heuristic_us"]) for e in autotune_table(n.value)]
+
+
+def autotune_table(n: int = None):
+    """The tuning table as a list of dicts (key, cfg, splits, choice, us, heuristic_us)."""
+    if n is None:
+        c = C.c_int32()
+        call("cpra_autotune_end", C.byref(c))  # reading the size also stops tuning
+        n = c.value
     out = []
-    for i in range(n.value):
+    for i in range(n):
         key, choice = C.create_string_buffer(256), C.create_string_buffer(64)
+        cfg, splits = C.c_int32(), C.c_int32()
         us, hus = C.c_double(), C.c_double()
-        call("cpra_autotune_get", i, key, 256, choice, 64, C.byref(us), C.byref(hus))
-        out.append((key.value.decode(), choice.value.decode(), us.value, hus.value))
+        call("cpra_autotune_get", i, key, 256, C.byref(cfg), C.byref(splits), choice, 64,
+             C.byref(us), C.byref(hus))
+        out.append({"key": key.value.decode(), "cfg": cfg.value, "splits": splits.value,
+                    "choice": choice.value.decode(), "us": us.value, "heuristic_us": hus.value})
     return out
+
+
+def autotune_set(key: str, cfg: int, splits: int) -> None:
+    call("cpra_autotune_set", key.encode(), int(cfg), int(splits))
 
 
 def autotune_reset() -> None:

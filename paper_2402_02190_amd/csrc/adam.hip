@@ -22,6 +22,7 @@ struct AdamArgs {
   double b1d, b2d;
   int t;
   const int32_t* step_counter;
+  int t_offset;  // t = *step_counter + t_offset when step_counter is given
 };
 
 struct AdamCoef {
@@ -41,7 +42,7 @@ template <bool VEC4>
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __shared__ float s_bc[2];
   if (threadIdx.x == 0) {
-    int t = a.step_counter ? (*a.step_counter + 1) : a.t;
+    int t = a.step_counter ? (*a.step_counter + a.t_offset) : a.t;
     double bc1 = 1.0 - pow(a.b1d, (double)t);
     double bc2 = 1.0 - pow(a.b2d, (double)t);
     s_bc[0] = (float)(1.0 / bc1);
@@ -82,13 +83,13 @@ inline bool al16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 
 
 cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
                       const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
-                      hipStream_t stream) {
+                      hipStream_t stream, int t_offset) {
   if (n == 0) return CPRA_OK;
   AdamArgs a{n, params, grads, m, v,
              (float)cfg->lr, (float)cfg->beta1, (float)(1.0 - cfg->beta1),
              (float)cfg->beta2, (float)(1.0 - cfg->beta2), (float)cfg->eps,
              (float)(1.0 - cfg->lr * cfg->weight_decay), cfg->beta1, cfg->beta2,
-             t, step_counter};
+             t, step_counter, t_offset};
   const bool vec = al16(params) && al16(grads) && al16(m) && al16(v);
   const int64_t work = vec ? (n + 3) / 4 : n;
   const int blocks = (int)std::min<int64_t>(ceil_div(work, 256), 256 * 8);

@@ -95,9 +95,11 @@ __device__ inline bool item_rows(int b, int n_graphs, int n_nodes, const int32_t
 
 // Fixed-order FP64 reduction of per-item partial columns into per-graph sums:
 // out[g*ncols + c] = sum over items of graph g of part[c*items_cap + item].
+// advance (optional): block (0, 0) also increments *advance once.
 cpra_status launch_segment_reduce(const cpra_csr* g, int rows_per_item, const int32_t* item_ptr,
                                   const float* part, const double* part64, int64_t items_cap,
-                                  int ncols, double* out, hipStream_t stream);
+                                  int ncols, double* out, hipStream_t stream,
+                                  int32_t* advance = nullptr);
 
 // ---- kernels used by the model orchestration ------------------------------
 struct GemmPiece {
@@ -139,15 +141,36 @@ cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t
                     hipStream_t stream);
 
 size_t loss_workspace_bytes(const cpra_csr* g, int S, bool need_p);
+// want_terms: the partials for the terms are needed (by a later loss_terms_reduce)
+// even if `terms` itself is NULL here.
 cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const float* Z, int64_t ldz,
                          const float* P, int64_t ldp, float* dZ, int64_t lddz, double* terms,
-                         void* ws, size_t ws_bytes, hipStream_t stream);
+                         void* ws, size_t ws_bytes, hipStream_t stream, bool want_terms = false);
 cpra_status check_loss_cfg_public(const cpra_csr* g, const cpra_loss_cfg* cfg);
 
+// With step_counter, Adam's t = *step_counter + t_offset.
 cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
                       const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
-                      hipStream_t stream);
+                      hipStream_t stream, int t_offset = 1);
 cpra_status check_adam_cfg(const cpra_adam_cfg* cfg);
+
+// Side stream of the current device (see streams.hip).  fork_to makes the side
+// stream wait for everything enqueued so far on `main`; join_from makes `main`
+// wait for everything enqueued so far on the side stream.
+struct SideStream {
+  hipStream_t stream;
+  hipEvent_t ev[2];
+};
+bool overlap_enabled();  // unless CPRA_OVERLAP=0 in the environment
+cpra_status get_side_stream(SideStream** out);
+cpra_status fork_to(SideStream* s, hipStream_t main);
+cpra_status join_from(SideStream* s, hipStream_t main);
+
+// The loss in two launches: the fused per-node kernel (dZ + per-item partials
+// in the workspace) and the per-graph FP64 reduction of the partials.
+// advance (optional): one thread of the reduction increments *advance.
+cpra_status loss_terms_reduce(const cpra_csr* g, const cpra_loss_cfg* cfg, double* terms, void* ws,
+                              hipStream_t stream, int32_t* advance = nullptr);
 
 cpra_status fill_i64(int64_t* p, int64_t n, int64_t value, hipStream_t stream);
 cpra_status increment_counter(int32_t* counter, hipStream_t stream);

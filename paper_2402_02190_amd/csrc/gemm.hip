@@ -12,7 +12,7 @@
 // consecutive floats per half-wavefront.  Interior tiles take unguarded
 // float4 loads (a uniform branch); edge tiles fall back to guarded loads.
 //
-// One launch runs up to four independent problems (grid.y = problem x split).
+// One launch runs up to four independent problems.
 // A problem's contraction may be split in two K pieces with separate
 // pointers, so [X | MX] [Ws | Wn]^T is a single GEMM without a concatenated
 // copy.  Split-K writes FP32 partial tiles that a second kernel sums in a
@@ -67,7 +67,7 @@ struct LaunchArgs {
   ProbDev p[kMaxProblems];
   int n_prob;
   int splits;
-  int grid_x;  // blocks per problem-split (a multiple of 8)
+  int grid_x;  // no split: blocks per problem (a multiple of 8); split-K: tiles per group
   float* partial;
 };
 
@@ -175,14 +175,27 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
   __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
 
-  const int prob = blockIdx.y / args.splits;
-  const int split = blockIdx.y % args.splits;
+  // XCD-aware order: the hardware deals consecutive block ids round-robin to
+  // the 8 XCDs, each with its own L2.
+  //  * no split (grid = tiles x problems): each XCD gets a contiguous run of
+  //    tiles, so neighbouring N tiles share their A panel in that XCD's L2;
+  //  * split-K (1-D grid): all tiles of one (problem, split) group -- which
+  //    read the same K rows of A and B -- go to the same XCD.
+  int prob, split, tile;
+  if (args.splits == 1) {
+    prob = blockIdx.y;
+    split = 0;
+    const int per_xcd = args.grid_x / 8;
+    tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  } else {
+    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int group = x + 8 * (j / args.grid_x);  // grid_x = tiles per group here
+    tile = j % args.grid_x;
+    if (group >= args.n_prob * args.splits) return;
+    prob = group / args.splits;
+    split = group % args.splits;
+  }
   const ProbDev& P = args.p[prob];
-  // XCD-aware order: hardware deals consecutive block ids round-robin to the 8
-  // XCDs; give each XCD a contiguous run of tiles (neighbouring N tiles share
-  // the A panel in that XCD's L2).
-  const int per_xcd = args.grid_x / 8;
-  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (tile >= P.tiles_m * P.tiles_n) return;
   const int tm_idx = tile / P.tiles_n;
   const int tn_idx = tile % P.tiles_n;
@@ -422,8 +435,15 @@ void launch_cfg(LaunchArgs& args, hipStream_t stream) {
     args.p[i].tiles_n = (int)ceil_div(args.p[i].n_eff, BN);
     max_tiles = max(max_tiles, args.p[i].tiles_m * args.p[i].tiles_n);
   }
-  args.grid_x = (int)ceil_div(max_tiles, 8) * 8;
-  dim3 grid(args.grid_x, args.n_prob * args.splits);
+  dim3 grid;
+  if (args.splits == 1) {
+    args.grid_x = (int)ceil_div(max_tiles, 8) * 8;
+    grid = dim3(args.grid_x, args.n_prob);
+  } else {
+    args.grid_x = max_tiles;  // tiles per (problem, split) group
+    const int64_t groups = (int64_t)args.n_prob * args.splits;
+    grid = dim3((unsigned)(ceil_div(groups, 8) * 8 * max_tiles));
+  }
   hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T>), grid, dim3(64 * WM * WN), 0, stream,
                      args);
 }
@@ -496,9 +516,12 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
     flops += 2.0 * mn * ((double)args.p[i].K[0] + (args.p[i].n_pieces > 1 ? args.p[i].K[1] : 0));
     red_bytes += 4.0 * mn * (pl.splits + 1);
   }
-  static const char* layout[2][2] = {{"gemm_nn", "gemm_nt"}, {"gemm_tn", "gemm_tt"}};
+  // profiler family = one kernel instantiation: layout + tile configuration
+  static const char* layout[2][2] = {{"nn", "nt"}, {"tn", "tt"}};
+  char pname[64];
+  snprintf(pname, sizeof(pname), "gemm_%s_%s", layout[a_t][b_t], kCfgNames[pl.cfg]);
   {
-    ProfScope ps(layout[a_t][b_t], stream, flops, 0.0);
+    ProfScope ps(pname, stream, flops, 0.0);
     if (!a_t && b_t) launch_any<false, true>(pl.cfg, args, stream);
     else if (!a_t && !b_t) launch_any<false, false>(pl.cfg, args, stream);
     else if (a_t && !b_t) launch_any<true, false>(pl.cfg, args, stream);
@@ -684,18 +707,31 @@ cpra_status cpra_autotune_reset(void) {
   return CPRA_OK;
 }
 
-cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, char* choice,
-                              size_t choice_len, double* us, double* heuristic_us) {
+cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, int32_t* cfg, int32_t* splits,
+                              char* choice, size_t choice_len, double* us, double* heuristic_us) {
   using namespace cpra;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (i < 0 || i >= (int32_t)g_order.size())
     CPRA_FAIL(CPRA_ERR_PARAM, "autotune_get: index out of range");
   const TuneEntry& e = g_table[g_order[i]];
   if (key && key_len) snprintf(key, key_len, "%s", g_order[i].c_str());
+  if (cfg) *cfg = e.plan.cfg;
+  if (splits) *splits = e.plan.splits;
   if (choice && choice_len)
     snprintf(choice, choice_len, "%s/split%d", kCfgNames[e.plan.cfg], e.plan.splits);
   if (us) *us = e.us;
   if (heuristic_us) *heuristic_us = e.heuristic_us;
+  return CPRA_OK;
+}
+
+cpra_status cpra_autotune_set(const char* key, int32_t cfg, int32_t splits) {
+  using namespace cpra;
+  if (key == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "autotune_set: key is NULL");
+  if (cfg < 0 || cfg >= kNumCfgs || splits < 1 || splits > 64)
+    CPRA_FAIL(CPRA_ERR_PARAM, "autotune_set: config %d / splits %d out of range", cfg, splits);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_table.find(key) == g_table.end()) g_order.push_back(key);
+  g_table[key] = TuneEntry{Plan{cfg, splits}, -1.0, -1.0};
   return CPRA_OK;
 }
 

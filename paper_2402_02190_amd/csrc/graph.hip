@@ -67,9 +67,11 @@ cpra_status launch_item_ptr(const cpra_csr* g, int R, int32_t* item_ptr, hipStre
 // fixed strided subset, then a fixed-shape tree.
 __global__ void k_segment_reduce(int n_graphs, int n_nodes, int R, const int32_t* __restrict__ item_ptr,
                                  const float* __restrict__ part, const double* __restrict__ part64,
-                                 int64_t items_cap, int ncols, double* __restrict__ out) {
+                                 int64_t items_cap, int ncols, double* __restrict__ out,
+                                 int32_t* advance) {
   int g = blockIdx.x;
   int c = blockIdx.y;
+  if (advance && g == 0 && c == 0 && threadIdx.x == 0) advance[0] = advance[0] + 1;
   int b0, b1;
   if (item_ptr == nullptr) {
     b0 = 0;
@@ -98,12 +100,13 @@ __global__ void k_segment_reduce(int n_graphs, int n_nodes, int R, const int32_t
 
 cpra_status launch_segment_reduce(const cpra_csr* g, int R, const int32_t* item_ptr,
                                   const float* part, const double* part64, int64_t items_cap,
-                                  int ncols, double* out, hipStream_t stream) {
+                                  int ncols, double* out, hipStream_t stream, int32_t* advance) {
   if (ncols <= 0) return CPRA_OK;
   dim3 grid(g->n_graphs, ncols);
   ProfScope ps("segment_reduce", stream, 0.0, (double)ncols * items_cap * (part64 ? 8.0 : 4.0));
   hipLaunchKernelGGL(k_segment_reduce, grid, dim3(256), 0, stream, g->n_graphs, g->n_nodes, R,
-                     g->n_graphs > 1 ? item_ptr : nullptr, part, part64, items_cap, ncols, out);
+                     g->n_graphs > 1 ? item_ptr : nullptr, part, part64, items_cap, ncols, out,
+                     advance);
   CPRA_CHECK_LAUNCH("segment_reduce");
   return CPRA_OK;
 }

@@ -256,16 +256,17 @@ struct LossWs {
   size_t p_off, item_off, part_off, total;
 };
 
+// Workspace: [item table][partials][P = sigmoid(Z) when the caller passes none].
 LossWs loss_ws_layout(const cpra_csr* g, int S, bool need_p) {
   LossGeom G = loss_geom(g, S);
   LossWs w{};
   size_t off = 0;
-  w.p_off = off;
-  if (need_p) off += align_up((size_t)g->n_nodes * S * sizeof(float), 256);
   w.item_off = off;
   off += align_up((size_t)(g->n_graphs + 1) * sizeof(int32_t), 256);
   w.part_off = off;
   off += align_up((size_t)(S + 2) * G.items_cap * sizeof(float), 256);
+  w.p_off = off;
+  if (need_p) off += align_up((size_t)g->n_nodes * S * sizeof(float), 256);
   w.total = off;
   return w;
 }
@@ -298,7 +299,8 @@ size_t loss_workspace_bytes(const cpra_csr* g, int S, bool need_p) {
 
 cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const float* Z, int64_t ldz,
                          const float* P, int64_t ldp, float* dZ, int64_t lddz, double* terms,
-                         void* ws, size_t ws_bytes, hipStream_t stream) {
+                         void* ws, size_t ws_bytes, hipStream_t stream, bool want_terms) {
+  want_terms = want_terms || terms != nullptr;
   const int S = cfg->S;
   LossWs L = loss_ws_layout(g, S, P == nullptr);
   if (ws == nullptr || ws_bytes < L.total)
@@ -322,7 +324,7 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.ddof = cfg->std_ddof;
   a.lpr_log2 = G.lpr_log2;
   a.iters = G.iters;
-  a.want_psi = terms != nullptr;
+  a.want_psi = want_terms ? 1 : 0;
   a.row_ptr = g->row_ptr;
   a.col_idx = g->col_idx;
   a.weight = g->weight;
@@ -368,10 +370,21 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
       CPRA_FAIL(CPRA_ERR_PARAM, "loss: S too large");
   }
   CPRA_CHECK_LAUNCH("loss");
-  if (terms)
-    CPRA_CHECK(launch_segment_reduce(g, G.R, item_ptr, part, nullptr, G.items_cap, S + 2, terms,
-                                     stream));
+  if (terms) CPRA_CHECK(loss_terms_reduce(g, cfg, terms, ws, stream));
   return CPRA_OK;
+}
+
+// Reduce the partials left in `ws` by the last loss launch on the same graph/config.
+cpra_status loss_terms_reduce(const cpra_csr* g, const cpra_loss_cfg* cfg, double* terms, void* ws,
+                              hipStream_t stream, int32_t* advance) {
+  const int S = cfg->S;
+  const LossWs L = loss_ws_layout(g, S, false);
+  const LossGeom G = loss_geom(g, S);
+  char* base = static_cast<char*>(ws);
+  const int32_t* item_ptr = reinterpret_cast<const int32_t*>(base + L.item_off);
+  const float* part = reinterpret_cast<const float*>(base + L.part_off);
+  return launch_segment_reduce(g, G.R, item_ptr, part, nullptr, G.items_cap, S + 2, terms, stream,
+                               advance);
 }
 
 }  // namespace cpra

@@ -200,9 +200,37 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
   return CPRA_OK;
 }
 
+// The weight-gradient GEMMs of a layer only feed the optimiser, so they run on
+// the side stream (when `side` is given) while the main stream computes the
+// input gradients.  The main stream waits for the side stream only before it
+// overwrites a buffer that forked side work still reads (and the caller joins
+// at the end).
+struct PendingReads {
+  const void* buf[4];
+  int n = 0;
+  void add(const void* p) {
+    if (n < 4) buf[n++] = p;
+  }
+  bool has(const void* p) const {
+    for (int i = 0; i < n; ++i)
+      if (buf[i] == p) return true;
+    return false;
+  }
+};
+
 cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params, const float* dZ,
-                          int64_t lddz, float* grads, void* ws, hipStream_t st) {
+                          int64_t lddz, float* grads, void* ws, hipStream_t st,
+                          SideStream* side) {
   const int N = g->n_nodes;
+  const hipStream_t wst = side ? side->stream : st;  // stream of the weight gradients
+  PendingReads pending;
+  auto before_write = [&](const void* buf) -> cpra_status {
+    if (side && pending.has(buf)) {
+      CPRA_CHECK(join_from(side, st));
+      pending.n = 0;
+    }
+    return CPRA_OK;
+  };
   const float* dY = dZ;
   int64_t lddy = lddz;
   int ping = 0;
@@ -220,7 +248,13 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
     const float* mask = (k == 0) ? nullptr : Hk;  // H_k = ReLU output of layer k-1
     if (l.lf) {
       float* T = fptr(ws, p.t_off);
+      CPRA_CHECK(before_write(T));
       CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
+      if (side) {
+        CPRA_CHECK(fork_to(side, st));
+        pending.add(dY);
+        pending.add(T);
+      }
       GemmProblem q[2] = {};
       for (int i = 0; i < 2; ++i) {
         q[i].piece[0] = GemmPiece{i == 0 ? dY : T, Hk, i == 0 ? lddy : l.out, ldh, N};
@@ -231,7 +265,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].N = l.in;
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
-      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
+      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
       GemmProblem r{};
       r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
       r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
@@ -242,12 +276,17 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       r.N = l.in;
       r.mask = mask;
       r.ld_mask = ldh;
+      CPRA_CHECK(before_write(dX));
       CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
     } else {
+      if (side) {
+        CPRA_CHECK(fork_to(side, st));
+        pending.add(dY);
+      }
       const float* AX;
       if (p.recompute) {
         float* buf = fptr(ws, p.ax_scratch_off);
-        CPRA_CHECK(aggregate(g, false, l.in, Hk, ldh, buf, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
+        CPRA_CHECK(aggregate(g, false, l.in, Hk, ldh, buf, l.in, nullptr, 0, nullptr, false, nullptr, 0, wst));
         AX = buf;
       } else {
         AX = fptr(ws, p.ax_off[k]);
@@ -262,7 +301,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].N = l.in;
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
-      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, st));
+      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
       float* G = fptr(ws, p.g_off);
       const int64_t ldg = 2 * l.in;
       GemmProblem r[2] = {};
@@ -275,6 +314,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         r[i].N = l.in;
       }
       CPRA_CHECK(gemm_batch(false, false, r, 2, nullptr, 0, st));
+      CPRA_CHECK(before_write(dX));
       CPRA_CHECK(aggregate(g, true, l.in, G + l.in, ldg, dX, lddx, G, ldg, nullptr, false, mask, ldh, st));
     }
     dY = dX;
@@ -352,7 +392,11 @@ cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, co
   make_plan(cfg, g->n_nodes, &p);
   if (ws == nullptr || ws_bytes < p.total)
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_backward: workspace %zu < %zu bytes", ws_bytes, p.total);
-  return backward_impl(g, p, params, dZ, lddz, grads, ws, as_stream(stream));
+  SideStream* side = nullptr;
+  if (overlap_enabled()) CPRA_CHECK(get_side_stream(&side));
+  CPRA_CHECK(backward_impl(g, p, params, dZ, lddz, grads, ws, as_stream(stream), side));
+  if (side) CPRA_CHECK(join_from(side, as_stream(stream)));
+  return CPRA_OK;
 }
 
 size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg) {
@@ -387,12 +431,25 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "train_step: workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t st = as_stream(stream);
   const int S = cfg->model.S;
+  SideStream* side = nullptr;
+  if (overlap_enabled()) CPRA_CHECK(get_side_stream(&side));
+  void* loss_ws = static_cast<char*>(ws) + model_bytes;
   CPRA_CHECK(forward_impl(g, p, params, Z, S, ws, st));
-  CPRA_CHECK(loss_fwd_bwd(g, &lc, Z, S, fptr(ws, p.p_off), S, dZ, S, terms,
-                          static_cast<char*>(ws) + model_bytes, ws_bytes - model_bytes, st));
-  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st));
-  CPRA_CHECK(adam_step(p.n_params, params, grads, m, v, &cfg->adam, t, step_counter, st));
-  if (step_counter) CPRA_CHECK(increment_counter(step_counter, st));
+  CPRA_CHECK(loss_fwd_bwd(g, &lc, Z, S, fptr(ws, p.p_off), S, dZ, S, nullptr, loss_ws,
+                          ws_bytes - model_bytes, st, terms != nullptr));
+  // The step counter advances (t -> t + 1) after the loss has read t and before
+  // Adam reads t + 1: done by one thread of the loss-term reduction, or by a
+  // one-thread kernel when no terms are wanted.
+  if (terms) {  // the per-graph loss terms are off the critical path
+    if (side) CPRA_CHECK(fork_to(side, st));
+    CPRA_CHECK(loss_terms_reduce(g, &lc, terms, loss_ws, side ? side->stream : st, step_counter));
+  } else if (step_counter) {
+    CPRA_CHECK(increment_counter(step_counter, st));
+  }
+  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side));
+  if (side) CPRA_CHECK(join_from(side, st));
+  CPRA_CHECK(adam_step(p.n_params, params, grads, m, v, &cfg->adam, t, step_counter, st,
+                       /*t_offset=*/0));
   return CPRA_OK;
 }
 

@@ -3,8 +3,8 @@
 // While profiling is on, every kernel launch of the library is bracketed by
 // two events recorded on the launch's own stream, and tagged with a short
 // kernel-family name and its algorithmic work (FLOPs for GEMMs, compulsory
-// HBM bytes for the memory-bound kernels).  Launches on a stream that is
-// being captured into a graph are not recorded.
+// HBM bytes for the memory-bound kernels).  Launches on a stream being
+// captured are not recorded.
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -72,22 +72,35 @@ ProfScope::~ProfScope() {
 extern "C" {
 
 cpra_status cpra_profile_begin(void) {
-  std::lock_guard<std::mutex> lk(cpra::g_mu);
-  cpra::g_on = true;
+  using namespace cpra;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Rec& r : g_recs) {
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  g_summary.clear();
+  g_on = true;
   return CPRA_OK;
 }
 
-cpra_status cpra_profile_end(int32_t* n_kernels) {
+cpra_status cpra_profile_stop(void) {
+  std::lock_guard<std::mutex> lk(cpra::g_mu);
+  cpra::g_on = false;
+  return CPRA_OK;
+}
+
+cpra_status cpra_profile_collect(void) {
   using namespace cpra;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_on = false;
   std::unordered_map<std::string, size_t> where;
-  g_summary.clear();
+  for (size_t i = 0; i < g_summary.size(); ++i) where[g_summary[i].name] = i;
   for (Rec& r : g_recs) {
     hipError_t e = hipEventSynchronize(r.b);
-    if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "profile_end: %s", hipGetErrorString(e));
+    if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "profile_collect: %s", hipGetErrorString(e));
     float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
+    e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "profile_collect: %s", hipGetErrorString(e));
     auto it = where.find(r.name);
     if (it == where.end()) {
       where[r.name] = g_summary.size();
@@ -99,6 +112,15 @@ cpra_status cpra_profile_end(int32_t* n_kernels) {
     s.total_ms += ms;
     s.flops += r.flops;
     s.bytes += r.bytes;
+  }
+  return CPRA_OK;
+}
+
+cpra_status cpra_profile_end(int32_t* n_kernels) {
+  using namespace cpra;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_on = false;
+  for (Rec& r : g_recs) {
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }

@@ -71,7 +71,7 @@ class CPRASolver:
             self.lam = torch.from_numpy(lam).to(device)
         else:
             self.lam = None
-        self.step_counter = torch.zeros(1, dtype=torch.int32, device=device)
+        self.step_counter = torch.zeros(1, dtype=torch.int32, device=device)  # steps done
         self.loss_cfg = api.make_loss_cfg(self.problem_id, S, self.lam, cfg.alpha, 0.0, cfg.nu,
                                           cfg.std_ddof, None, cfg.gamma_start, cfg.gamma_end, cfg.T)
         self.adam_cfg = api.AdamCfg(cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay)
@@ -154,11 +154,11 @@ class CPRASolver:
             table = api.autotune_end()
         return table
 
-    def capture(self) -> None:
-        """Record one training step into a HIP graph on a private stream."""
-        if self._graph is not None:
-            return
-        self._stream = torch.cuda.Stream()
+    def capture_step(self):
+        """Record one training step into a new HIP graph on the solver's private
+        stream and return its handle (the caller destroys it)."""
+        if self._stream is None:
+            self._stream = torch.cuda.Stream()
         self._stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self._stream):
             api.capture_begin(self._stream)
@@ -168,7 +168,12 @@ class CPRASolver:
                                self._stream)
             finally:
                 g = api.capture_end(self._stream)
-        self._graph = g
+        return g
+
+    def capture(self) -> None:
+        """Record one training step into the solver's HIP graph (once)."""
+        if self._graph is None:
+            self._graph = self.capture_step()
 
     def replay(self, n: int = 1) -> None:
         if self._graph is None:
