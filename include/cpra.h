@@ -210,6 +210,15 @@ cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, co
                                 const float* dZ, int64_t lddz, float* grads,
                                 void* ws, size_t ws_bytes, cpra_stream_t stream);
 
+/* The input of layer `layer` (1 <= layer < n_layers), i.e. the ReLU output of
+ * layer - 1, as saved in ws by the last cpra_model_forward / cpra_train_step
+ * on that workspace: a device pointer into ws ([N, hidden], leading dim *ld),
+ * valid until the workspace is reused.  Its positive entries are the units
+ * whose ReLU derivative the backward takes as 1. */
+cpra_status cpra_model_saved_activation(const cpra_csr* g, const cpra_model_cfg* cfg, void* ws,
+                                        size_t ws_bytes, int32_t layer, const float** out,
+                                        int64_t* ld);
+
 /* ------------------------------------------------------------------------
  * Adam / AdamW (Sec. 4.1 Implementation and the training-setting appendix;
  * Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

@@ -55,8 +55,16 @@ def forward(params: Dict[str, object], M: sp.csr_matrix):
     return H, cache
 
 
-def backward(params: Dict[str, object], M: sp.csr_matrix, cache, dZ: np.ndarray):
-    """Gradients of a scalar loss with dLoss/dZ = dZ, by the chain rule through ``forward``."""
+def backward(params: Dict[str, object], M: sp.csr_matrix, cache, dZ: np.ndarray,
+             relu_active=None):
+    """Gradients of a scalar loss with dLoss/dZ = dZ, by the chain rule through ``forward``.
+
+    ``relu_active`` (optional): per hidden layer k (0-based, all but the last), a
+    boolean array [N, out_k] of the units on the positive side of their ReLU.
+    By default the oracle's own pre-activations decide (Y > 0); a comparison
+    with a lower-precision forward passes that forward's decisions instead, so
+    that both sides take the ReLU's derivative at the same (discrete) point.
+    """
     grads = {"layers": [None] * len(params["layers"])}
     dY = np.asarray(dZ, dtype=np.float64)
     MT = M.T.tocsr()
@@ -64,7 +72,8 @@ def backward(params: Dict[str, object], M: sp.csr_matrix, cache, dZ: np.ndarray)
         L = params["layers"][k]
         c = cache[k]
         if k < len(params["layers"]) - 1:
-            dY = dY * (c["Y"] > 0.0)
+            active = (c["Y"] > 0.0) if relu_active is None else relu_active[k]
+            dY = dY * active
         g = {"Ws": dY.T @ c["H"], "Wn": dY.T @ c["agg"]}
         if "b" in L:
             g["b"] = dY.sum(axis=0)

@@ -67,8 +67,11 @@ class StepConfig:
     weight_decay: float = 0.0
 
 
-def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float):
-    """Forward, loss terms (per graph of a batch) and all parameter gradients."""
+def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=None,
+                   return_cache: bool = False):
+    """Forward, loss terms (per graph of a batch) and all parameter gradients.
+
+    ``relu_active``: optional ReLU decisions per hidden layer (see gnn.backward)."""
     Z, cache = gnn.forward(params, M)
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     if gp.size > 2:
@@ -84,7 +87,9 @@ def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float):
                                       cfg.nu, cfg.ddof)]
         dZ = objective.grad_wrt_Z(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha, cfg.nu,
                                   cfg.ddof)
-    grads = gnn.backward(params, M, cache, dZ)
+    grads = gnn.backward(params, M, cache, dZ, relu_active)
+    if return_cache:
+        return Z, terms, dZ, grads, cache
     return Z, terms, dZ, grads
 
 

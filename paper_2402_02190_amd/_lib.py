@@ -76,6 +76,8 @@ PROTOTYPES = {
     "cpra_model_workspace_bytes": (SZ, [PCsr, PModel]),
     "cpra_model_forward": (None, [PCsr, PModel, P, P, I64, P, SZ, P]),
     "cpra_model_backward": (None, [PCsr, PModel, P, P, I64, P, P, SZ, P]),
+    "cpra_model_saved_activation": (None, [PCsr, PModel, P, SZ, I32, C.POINTER(C.c_void_p),
+                                           C.POINTER(I64)]),
     "cpra_adam_step": (None, [I64, P, P, P, P, PAdam, I32, P, P]),
     "cpra_train_step_workspace_bytes": (SZ, [PCsr, PStep]),
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),

@@ -188,6 +188,18 @@ def model_backward(g, cfg: ModelCfg, params: torch.Tensor, dZ: torch.Tensor, gra
     return grads
 
 
+def model_saved_activation(g, cfg: ModelCfg, ws: torch.Tensor, layer: int, n_nodes: int,
+                           width: int) -> torch.Tensor:
+    """A copy of the saved input of `layer` (the ReLU output of layer - 1)."""
+    ptr = C.c_void_p()
+    ld = C.c_int64()
+    call("cpra_model_saved_activation", _csr(g), C.byref(cfg), _ptr(ws), ws.numel(), layer,
+         C.byref(ptr), C.byref(ld))
+    off = ptr.value - ws.data_ptr()
+    flat = ws[off: off + n_nodes * ld.value * 4].view(torch.float32)
+    return flat.view(n_nodes, ld.value)[:, :width].clone()
+
+
 def adam_step(params, grads, m, v, cfg: AdamCfg, t: int = 1, step_counter=None, stream=None):
     call("cpra_adam_step", params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v),
          C.byref(cfg), int(t), _ptr(step_counter), _stream(stream))

@@ -399,6 +399,23 @@ cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, co
   return CPRA_OK;
 }
 
+cpra_status cpra_model_saved_activation(const cpra_csr* g, const cpra_model_cfg* cfg, void* ws,
+                                        size_t ws_bytes, int32_t layer, const float** out,
+                                        int64_t* ld) {
+  using namespace cpra;
+  CPRA_CHECK(check_graph_and_model(g, cfg, "model_saved_activation"));
+  if (out == nullptr || ld == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "model_saved_activation: NULL output");
+  if (layer < 1 || layer >= cfg->n_layers)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model_saved_activation: layer %d outside 1..%d", layer, cfg->n_layers - 1);
+  Plan p{};
+  make_plan(cfg, g->n_nodes, &p);
+  if (ws == nullptr || ws_bytes < p.total)
+    CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_saved_activation: workspace %zu < %zu bytes", ws_bytes, p.total);
+  *out = fptr(ws, p.h_off[layer]);
+  *ld = p.layer[layer].in;
+  return CPRA_OK;
+}
+
 size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg) {
   if (g == nullptr || cfg == nullptr || cpra::check_model_cfg(&cfg->model) != CPRA_OK) return 0;
   cpra::Plan p{};

@@ -128,6 +128,15 @@ class CPRASolver:
             d_in = d_out
         return out
 
+    def relu_active(self):
+        """Per hidden layer, the boolean [N, hidden] ReLU decisions of the last forward."""
+        out = []
+        for k in range(1, self.model_cfg.n_layers):
+            H = api.model_saved_activation(self.graph, self.model_cfg, self.ws, k, self.graph.n,
+                                           self.cfg.hidden)
+            out.append((H > 0).cpu().numpy())
+        return out
+
     def loss_workspace(self) -> torch.Tensor:
         """A workspace for standalone loss calls (computes P itself), allocated once."""
         if getattr(self, "_loss_ws", None) is None:
