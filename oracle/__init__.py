@@ -24,6 +24,9 @@ Solutions in Combinatorial Optimization Problems", TMLR 2025):
   violations, cut value, DScore (Sec. 4.1 Evaluation Metrics) and the
   max-sum Hamming distance (Proposition 3.2).
 * ``exact`` -- brute-force and MILP optima for small graphs.
+* ``warmstart`` -- the learned warm start: bfloat16 rounding, triangle counts
+  and clustering features, the BF16 message-passing network, its backward and
+  its training objective (CPRA loss + distillation onto converged solutions).
 
 Pins (tests marked ``not gpu``) tie each function to something other than
 itself: the relaxed loss equals the discrete objective on {0,1} (checked

@@ -40,8 +40,11 @@ def to_f64(params: Dict[str, object]) -> Dict[str, object]:
                        for L in params["layers"]]}
 
 
-def forward(params: Dict[str, object], M: sp.csr_matrix):
-    """Returns (Z, cache).  cache holds each layer's input, aggregate and pre-activation."""
+def forward(params: Dict[str, object], M: sp.csr_matrix, z_offset=None):
+    """Returns (Z, cache).  cache holds each layer's input, aggregate and pre-activation.
+
+    z_offset (optional, [N, S]): fixed logits added to the network's output, so
+    that P = sigmoid(GNN(G) + z_offset) -- the warm start of a learned proposal."""
     H = params["emb"]
     cache: List[Dict[str, np.ndarray]] = []
     n_layers = len(params["layers"])
@@ -52,6 +55,8 @@ def forward(params: Dict[str, object], M: sp.csr_matrix):
             Y = Y + L["b"][None, :]
         cache.append({"H": H, "agg": agg, "Y": Y})
         H = np.maximum(Y, 0.0) if k < n_layers - 1 else Y
+    if z_offset is not None:
+        H = H + np.asarray(z_offset, dtype=np.float64)
     return H, cache
 
 

@@ -68,11 +68,12 @@ class StepConfig:
 
 
 def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=None,
-                   return_cache: bool = False):
+                   return_cache: bool = False, z_offset=None):
     """Forward, loss terms (per graph of a batch) and all parameter gradients.
 
-    ``relu_active``: optional ReLU decisions per hidden layer (see gnn.backward)."""
-    Z, cache = gnn.forward(params, M)
+    ``relu_active``: optional ReLU decisions per hidden layer (see gnn.backward).
+    ``z_offset``: optional warm-start logits added to the output (see gnn.forward)."""
+    Z, cache = gnn.forward(params, M, z_offset)
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     if gp.size > 2:
         terms = objective.batched_loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
@@ -113,7 +114,7 @@ class AdamState:
 
 
 def solve(params_f32, graph, cfg: StepConfig, T: int, gamma_start: float, gamma_end: float,
-          record_every: int = 0) -> Dict[str, object]:
+          record_every: int = 0, z_offset=None) -> Dict[str, object]:
     """Run T training steps from the given initial parameters; round and evaluate."""
     params = gnn.to_f64(params_f32)
     M = gnn.mean_aggregation_matrix(graph.row_ptr, graph.col_idx)
@@ -121,11 +122,11 @@ def solve(params_f32, graph, cfg: StepConfig, T: int, gamma_start: float, gamma_
     history: List[Dict[str, object]] = []
     for t in range(T):
         gamma = gamma_at(t, T, gamma_start, gamma_end)
-        Z, terms, dZ, grads = loss_and_grads(params, M, graph, cfg, gamma)
+        Z, terms, dZ, grads = loss_and_grads(params, M, graph, cfg, gamma, z_offset=z_offset)
         if record_every and (t % record_every == 0 or t == T - 1):
             history.append({"t": t, "gamma": gamma, "terms": terms})
         opt.step(params, grads, cfg)
-    Z, _ = gnn.forward(params, M)
+    Z, _ = gnn.forward(params, M, z_offset)
     X = evaluate.round_solutions(Z)
     ev = evaluate.evaluate(X, graph, cfg.problem)
     return {"Z": Z, "X": X, "eval": ev, "params": params, "history": history}

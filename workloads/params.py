@@ -82,3 +82,22 @@ def random_logits(n: int, S: int, seed: int, scale: float = 2.0,
         sgn = np.where(rng.random((n, S)) < 0.5, -1.0, 1.0)
         return (mag * sgn).astype(np.float32)
     return (scale * rng.standard_normal((n, S))).astype(np.float32)
+
+
+def init_mpnn_params(in_dim: int, hidden: int, S: int, n_layers: int, seed: int):
+    """Seeded float32 weights of the warm-start network (GraphSAGE form with bias):
+    per layer Ws, Wn [out_k, in_k] ~ U(-1/sqrt(in_k), 1/sqrt(in_k)), b [out_k] = 0."""
+    rng = np.random.default_rng(seed)
+    layers: List[Dict[str, np.ndarray]] = []
+    for d_in, d_out in layer_dims(n_layers, in_dim, hidden, S):
+        bound = 1.0 / np.sqrt(d_in)
+        layers.append({"Ws": rng.uniform(-bound, bound, (d_out, d_in)).astype(np.float32),
+                       "Wn": rng.uniform(-bound, bound, (d_out, d_in)).astype(np.float32),
+                       "b": np.zeros(d_out, dtype=np.float32)})
+    return {"layers": layers}
+
+
+def random_channels(n: int, R: int, seed: int) -> np.ndarray:
+    """Seeded per-node random input channels ~ U(-1, 1), float32 [n, R]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, (n, R)).astype(np.float32)
