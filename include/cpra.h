@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 1
+#define CPRA_ABI_VERSION 2
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -190,6 +190,11 @@ typedef struct {
   int32_t hidden;     /* hidden width (>= 1) */
   int32_t S;          /* output width = heads (>= 1) */
   int32_t recompute;  /* 1: backward recomputes neighbour aggregates instead of keeping them */
+  /* Optional device [N, S] (contiguous) fixed logits added to the output layer:
+   * Z = GNN(G) + z_offset, i.e. P = sigmoid(GNN(G) + z_offset).  This is how a
+   * learned warm start (cpra_mpnn_forward) enters CPRA; the backward is
+   * unchanged (dZ/d offset = 1, the offset is not trained).  NULL: none. */
+  const float* z_offset;
 } cpra_model_cfg;
 
 /* Total float count including the embedding; -1 on invalid config. */
@@ -277,6 +282,95 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
                             int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
                             int64_t* violations, double* wvalue, int64_t* pair_hamming,
                             void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start.  The background section's paragraph on learning
+ * generalized heuristics from data describes networks trained over many
+ * instances that propose a starting point (a meta-learned initialisation) for
+ * a new one.  Here a small message-passing network maps per-node structural
+ * features to S logits Z_w, and CPRA then trains on
+ * P = sigmoid(GNN(G) + Z_w) (cpra_model_cfg.z_offset).
+ *
+ * bfloat16 tensors cross the ABI as uint16_t bit patterns, rounded to
+ * nearest-even from float32 (finite values).
+ * ---------------------------------------------------------------------- */
+
+/* Features of every node, bf16 [N, in_dim] (ld_feat >= in_dim):
+ *   column 0: d_i / 16;  column 1: local clustering 2 T_i / (d_i (d_i - 1))
+ *   (0 if d_i < 2; formed in FP64, rounded to FP32, then to bf16);
+ *   columns 2 .. 1 + n_rand: rand [N, n_rand] (ld_rand), caller-drawn;
+ *   remaining columns: 0.
+ * T_i = number of triangles through i, i.e. pairs of adjacent neighbours
+ * (exact integers; written to triangles [N] when non-NULL).  Needs the
+ * rows of the CSR sorted (cpra_csr_validate_host).  in_dim >= 2 + n_rand. */
+cpra_status cpra_node_features(const cpra_csr* g, int32_t in_dim, int32_t n_rand,
+                               const float* rand, int64_t ld_rand, uint16_t* feat, int64_t ld_feat,
+                               int64_t* triangles, cpra_stream_t stream);
+
+/* The network: n_layers layers of the GraphSAGE form (GNN appendix, with
+ * one bias per layer), widths in_dim -> hidden -> ... -> S:
+ *   A_k = bf16(M H_{k-1});  Y_k = H_{k-1} bf16(Ws_k)^T + A_k bf16(Wn_k)^T + b_k
+ *   H_k = bf16(relu(Y_k)) (hidden layers);  Z_w = Y_L (float32)
+ * with H_0 the features.  Products run on bf16 matrix cores with FP32
+ * accumulation.  Parameters are float32 masters, per layer Ws [out, in],
+ * Wn [out, in], b [out] (cpra_mpnn_param_offsets); they are rounded to bf16
+ * inside every forward.  Limits: in_dim in {16, 32, 48, 64}; hidden in
+ * {32, 64}; S a multiple of 32 up to 128. */
+typedef struct {
+  int32_t n_layers; /* 1..8 */
+  int32_t in_dim;
+  int32_t hidden;
+  int32_t S;
+} cpra_mpnn_cfg;
+
+/* Float count of the parameter vector; -1 on an invalid config. */
+int64_t cpra_mpnn_param_count(const cpra_mpnn_cfg* cfg);
+/* offsets: host array of 3*n_layers entries (Ws, Wn, b per layer). */
+cpra_status cpra_mpnn_param_offsets(const cpra_mpnn_cfg* cfg, int64_t* offsets);
+size_t cpra_mpnn_workspace_bytes(const cpra_csr* g, const cpra_mpnn_cfg* cfg);
+/* Z_w [N, S] contiguous.  feat: bf16 [N, in_dim] contiguous, 16-byte aligned.
+ * Keeps the bf16 weights and activations the backward needs in ws. */
+cpra_status cpra_mpnn_forward(const cpra_csr* g, const cpra_mpnn_cfg* cfg, const float* params,
+                              const uint16_t* feat, float* Zw, void* ws, size_t ws_bytes,
+                              cpra_stream_t stream);
+/* Hand-written backward of the immediately preceding cpra_mpnn_forward on the
+ * same ws: grads (param layout, fully overwritten) of a loss with gradient dZw
+ * [N, S] (contiguous float32) w.r.t. Z_w.  Rounding points: dY_L = bf16(dZw);
+ * dY_{k-1} = bf16((G_s + M^T G_n) * [H_{k-1} > 0]) with G = dY_k [bf16(Ws) |
+ * bf16(Wn)] in FP32; weight and bias gradients in FP32, summed over fixed
+ * row blocks in a fixed order (deterministic). */
+cpra_status cpra_mpnn_backward(const cpra_csr* g, const cpra_mpnn_cfg* cfg, const uint16_t* feat,
+                               const float* dZw, float* grads, void* ws, size_t ws_bytes,
+                               cpra_stream_t stream);
+/* A device pointer into ws to a tensor saved by the last forward: which = 0,
+ * the bf16 input H of layer `layer` (layer >= 1); which = 1, its bf16
+ * aggregate A = M H.  [N, in_layer] with leading dimension *ld. */
+cpra_status cpra_mpnn_saved(const cpra_csr* g, const cpra_mpnn_cfg* cfg, void* ws, size_t ws_bytes,
+                            int32_t layer, int32_t which, const uint16_t** out, int64_t* ld);
+/* dZ += beta * (sigmoid(Z) - target): the gradient of beta * sum BCE(sigmoid(Z),
+ * target) with logits Z.  target uint8 {0, 1} [n_rows, S] (ldt). */
+cpra_status cpra_bce_grad(int32_t n_rows, int32_t S, const float* Z, int64_t ldz,
+                          const uint8_t* target, int64_t ldt, float beta, float* dZ, int64_t lddz,
+                          cpra_stream_t stream);
+
+/* One training step of the network on a (batched) graph: forward; the CPRA
+ * loss of P = sigmoid(Z_w) and its gradient (cpra_loss_fwd_bwd, per graph of
+ * the batch); + beta * BCE towards target (converged CPRA solutions, uint8
+ * [N, S] contiguous; skipped if NULL or beta = 0); backward; Adam.  Counter,
+ * gamma and t semantics as cpra_train_step (loss.gamma_start = gamma_end for
+ * a fixed gamma). */
+typedef struct {
+  cpra_mpnn_cfg net;
+  cpra_loss_cfg loss;
+  cpra_adam_cfg adam;
+  float beta;
+} cpra_mpnn_step_cfg;
+size_t cpra_mpnn_train_step_workspace_bytes(const cpra_csr* g, const cpra_mpnn_step_cfg* cfg);
+cpra_status cpra_mpnn_train_step(const cpra_csr* g, const cpra_mpnn_step_cfg* cfg, float* params,
+                                 float* grads, float* m, float* v, const uint16_t* feat,
+                                 const uint8_t* target, float* Zw, float* dZw, double* terms,
+                                 int32_t t, int32_t* step_counter, void* ws, size_t ws_bytes,
+                                 cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Captured step graphs: enqueue work between begin/end on a non-null stream

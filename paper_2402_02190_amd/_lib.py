@@ -41,7 +41,8 @@ class LossCfg(C.Structure):
 
 class ModelCfg(C.Structure):
     _fields_ = [("layer_kind", C.c_int32), ("n_layers", C.c_int32), ("in_dim", C.c_int32),
-                ("hidden", C.c_int32), ("S", C.c_int32), ("recompute", C.c_int32)]
+                ("hidden", C.c_int32), ("S", C.c_int32), ("recompute", C.c_int32),
+                ("z_offset", C.c_void_p)]
 
 
 class AdamCfg(C.Structure):
@@ -53,8 +54,18 @@ class StepCfg(C.Structure):
     _fields_ = [("model", ModelCfg), ("loss", LossCfg), ("adam", AdamCfg)]
 
 
+class MpnnCfg(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("in_dim", C.c_int32), ("hidden", C.c_int32),
+                ("S", C.c_int32)]
+
+
+class MpnnStepCfg(C.Structure):
+    _fields_ = [("net", MpnnCfg), ("loss", LossCfg), ("adam", AdamCfg), ("beta", C.c_float)]
+
+
 P = C.c_void_p
 I32, I64, F32, SZ = C.c_int32, C.c_int64, C.c_float, C.c_size_t
+PMpnn, PMpnnStep = C.POINTER(MpnnCfg), C.POINTER(MpnnStepCfg)
 PCsr, PLoss, PModel, PAdam, PStep = (C.POINTER(Csr), C.POINTER(LossCfg), C.POINTER(ModelCfg),
                                      C.POINTER(AdamCfg), C.POINTER(StepCfg))
 
@@ -83,6 +94,18 @@ PROTOTYPES = {
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),
     "cpra_round_eval_workspace_bytes": (SZ, [PCsr, I32]),
     "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, SZ, P]),
+    "cpra_node_features": (None, [PCsr, I32, I32, P, I64, P, I64, P, P]),
+    "cpra_mpnn_param_count": (I64, [PMpnn]),
+    "cpra_mpnn_param_offsets": (None, [PMpnn, C.POINTER(I64)]),
+    "cpra_mpnn_workspace_bytes": (SZ, [PCsr, PMpnn]),
+    "cpra_mpnn_forward": (None, [PCsr, PMpnn, P, P, P, P, SZ, P]),
+    "cpra_mpnn_backward": (None, [PCsr, PMpnn, P, P, P, P, SZ, P]),
+    "cpra_mpnn_saved": (None, [PCsr, PMpnn, P, SZ, I32, I32, C.POINTER(C.c_void_p),
+                               C.POINTER(I64)]),
+    "cpra_bce_grad": (None, [I32, I32, P, I64, P, I64, F32, P, I64, P]),
+    "cpra_mpnn_train_step_workspace_bytes": (SZ, [PCsr, PMpnnStep]),
+    "cpra_mpnn_train_step": (None, [PCsr, PMpnnStep, P, P, P, P, P, P, P, P, P, I32, P, P, SZ,
+                                    P]),
     "cpra_capture_begin": (None, [P]),
     "cpra_capture_end": (None, [P, C.POINTER(C.c_void_p)]),
     "cpra_graph_launch": (None, [P, P]),

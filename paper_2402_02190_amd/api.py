@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 from ._lib import (GCN, MAXCUT, MIS, SAGE, AdamCfg, CpraError, Csr, LossCfg, ModelCfg,  # noqa: F401
-                   StepCfg, call)
+                   MpnnCfg, MpnnStepCfg, StepCfg, call)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -153,8 +153,15 @@ def sigmoid(Z: torch.Tensor, P: torch.Tensor, stream=None):
 
 
 def make_model_cfg(layer_kind: int, n_layers: int, in_dim: int, hidden: int, S: int,
-                   recompute: bool = False) -> ModelCfg:
-    return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute))
+                   recompute: bool = False, z_offset: torch.Tensor = None) -> ModelCfg:
+    """z_offset: optional float32 [N, S] contiguous device tensor of fixed logits added to
+    the output (the warm start); the caller keeps it alive while the config is used."""
+    if z_offset is not None:
+        if z_offset.dtype != torch.float32 or not z_offset.is_contiguous() or z_offset.dim() != 2 \
+                or z_offset.shape[1] != S:
+            raise ValueError("z_offset must be a contiguous float32 [N, S] tensor")
+    return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute),
+                    None if z_offset is None else z_offset.data_ptr())
 
 
 def model_param_count(cfg: ModelCfg, n_nodes: int) -> int:
@@ -228,6 +235,84 @@ def round_eval(g, problem: int, Z: torch.Tensor, X=None, value=None, violations=
     call("cpra_round_eval", _csr(g), problem, S, _ptr(Z), Z.stride(0), _ptr(X),
          0 if X is None else X.stride(0), _ptr(value), _ptr(violations), _ptr(wvalue),
          _ptr(pair_hamming), _ptr(ws), ws.numel(), _stream(stream))
+
+
+# ---------------------------------------------------------------- warm start
+def node_features(g, in_dim: int, rand: Optional[torch.Tensor], feat: torch.Tensor,
+                  triangles: Optional[torch.Tensor] = None, stream=None):
+    """feat: int16 (bf16 bit patterns) [N, in_dim] device tensor; rand: float32
+    [N, n_rand] or None; triangles: int64 [N] or None."""
+    n_rand = 0 if rand is None else rand.shape[1]
+    call("cpra_node_features", _csr(g), in_dim, n_rand, _ptr(rand),
+         0 if rand is None else rand.stride(0), _ptr(feat), feat.stride(0), _ptr(triangles),
+         _stream(stream))
+    return feat
+
+
+def make_mpnn_cfg(n_layers: int, in_dim: int, hidden: int, S: int) -> MpnnCfg:
+    return MpnnCfg(n_layers, in_dim, hidden, S)
+
+
+def mpnn_param_count(cfg: MpnnCfg) -> int:
+    n = int(_lib.lib().cpra_mpnn_param_count(C.byref(cfg)))
+    if n < 0:
+        raise CpraError(4, "invalid mpnn config")
+    return n
+
+
+def mpnn_param_offsets(cfg: MpnnCfg):
+    out = (C.c_int64 * (3 * cfg.n_layers))()
+    call("cpra_mpnn_param_offsets", C.byref(cfg), out)
+    return list(out)
+
+
+def mpnn_workspace_bytes(g, cfg: MpnnCfg) -> int:
+    return int(_lib.lib().cpra_mpnn_workspace_bytes(_csr(g), C.byref(cfg)))
+
+
+def mpnn_forward(g, cfg: MpnnCfg, params, feat, Zw, ws, stream=None):
+    call("cpra_mpnn_forward", _csr(g), C.byref(cfg), _ptr(params), _ptr(feat), _ptr(Zw),
+         _ptr(ws), ws.numel(), _stream(stream))
+    return Zw
+
+
+def mpnn_backward(g, cfg: MpnnCfg, feat, dZw, grads, ws, stream=None):
+    call("cpra_mpnn_backward", _csr(g), C.byref(cfg), _ptr(feat), _ptr(dZw), _ptr(grads),
+         _ptr(ws), ws.numel(), _stream(stream))
+    return grads
+
+
+def mpnn_saved(g, cfg: MpnnCfg, ws: torch.Tensor, layer: int, which: int, n_nodes: int):
+    """A copy (int16 bf16 patterns) of a tensor saved by the last mpnn_forward:
+    which = 0: the input H of `layer` (>= 1); which = 1: its aggregate M H."""
+    ptr = C.c_void_p()
+    ld = C.c_int64()
+    call("cpra_mpnn_saved", _csr(g), C.byref(cfg), _ptr(ws), ws.numel(), layer, which,
+         C.byref(ptr), C.byref(ld))
+    off = ptr.value - ws.data_ptr()
+    flat = ws[off: off + n_nodes * ld.value * 2].view(torch.int16)
+    return flat.view(n_nodes, ld.value).clone()
+
+
+def bce_grad(Z: torch.Tensor, target: torch.Tensor, beta: float, dZ: torch.Tensor, stream=None):
+    call("cpra_bce_grad", Z.shape[0], Z.shape[1], _ptr(Z), Z.stride(0), _ptr(target),
+         target.stride(0), float(beta), _ptr(dZ), dZ.stride(0), _stream(stream))
+    return dZ
+
+
+def make_mpnn_step_cfg(net: MpnnCfg, loss: LossCfg, adam: AdamCfg, beta: float) -> MpnnStepCfg:
+    return MpnnStepCfg(net, loss, adam, float(beta))
+
+
+def mpnn_train_step_workspace_bytes(g, cfg: MpnnStepCfg) -> int:
+    return int(_lib.lib().cpra_mpnn_train_step_workspace_bytes(_csr(g), C.byref(cfg)))
+
+
+def mpnn_train_step(g, cfg: MpnnStepCfg, params, grads, m, v, feat, target, Zw, dZw, terms, ws,
+                    t: int = 1, step_counter=None, stream=None):
+    call("cpra_mpnn_train_step", _csr(g), C.byref(cfg), _ptr(params), _ptr(grads), _ptr(m),
+         _ptr(v), _ptr(feat), _ptr(target), _ptr(Zw), _ptr(dZw), _ptr(terms), int(t),
+         _ptr(step_counter), _ptr(ws), ws.numel(), _stream(stream))
 
 
 def capture_begin(stream) -> None:

@@ -76,6 +76,8 @@ struct AggArgs {
   int64_t ld_mask;
   float* sig_out;  // optional sigmoid(Y) [N, width] (ld_sig)
   int64_t ld_sig;
+  const float* add2;  // optional second addend [N, width] (ld_add2)
+  int64_t ld_add2;
 };
 
 __device__ inline float sigmoid_of(float z) {
@@ -148,6 +150,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
     V r = acc[c];
     if constexpr (!TRANS) O::scale(r, rs);
     if (a.add) O::add(r, *reinterpret_cast<const V*>(a.add + (int64_t)row * a.ld_add + u * VEC));
+    if (a.add2) O::add(r, *reinterpret_cast<const V*>(a.add2 + (int64_t)row * a.ld_add2 + u * VEC));
     if (a.bias) O::add(r, *reinterpret_cast<const V*>(a.bias + u * VEC));
     if (a.relu || a.mask) {
       V mk = O::zero();
@@ -178,7 +181,8 @@ template <int VEC, bool TRANS>
 cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, int64_t nnz) {
   // compulsory bytes: X once, Y written, add/mask read, CSR, inv_deg
   const double nw = (double)a.n * a.width * 4.0;
-  const double bytes = nw * (2.0 + (a.add ? 1.0 : 0.0) + (a.mask ? 1.0 : 0.0) + (a.sig_out ? 1.0 : 0.0)) +
+  const double bytes = nw * (2.0 + (a.add ? 1.0 : 0.0) + (a.add2 ? 1.0 : 0.0) +
+                             (a.mask ? 1.0 : 0.0) + (a.sig_out ? 1.0 : 0.0)) +
                        4.0 * (double)nnz + 8.0 * (double)a.n + 4.0;
   ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes);
   switch (nc) {
@@ -204,15 +208,16 @@ cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, 
 cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
                       float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
                       bool relu, const float* mask, int64_t ld_mask, hipStream_t stream,
-                      float* sig_out, int64_t ld_sig) {
+                      float* sig_out, int64_t ld_sig, const float* add2, int64_t ld_add2) {
   if (g->n_nodes == 0 || width == 0) return CPRA_OK;
   int vec = 1;
   for (int v : {4, 2}) {
     int vb = v * 4;
     if (width % v == 0 && ldx % v == 0 && ldy % v == 0 && (add == nullptr || ld_add % v == 0) &&
         (mask == nullptr || ld_mask % v == 0) && (sig_out == nullptr || ld_sig % v == 0) &&
-        aligned(X, vb) && aligned(Y, vb) && aligned(add, vb) && aligned(bias, vb) &&
-        aligned(mask, vb) && aligned(sig_out, vb)) {
+        (add2 == nullptr || ld_add2 % v == 0) && aligned(X, vb) && aligned(Y, vb) &&
+        aligned(add, vb) && aligned(bias, vb) && aligned(mask, vb) && aligned(sig_out, vb) &&
+        aligned(add2, vb)) {
       vec = v;
       break;
     }
@@ -227,7 +232,7 @@ cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float*
   while (nc < need) nc <<= 1;
   if (nc > 16) CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate: width %d exceeds 4096", width);
   AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
-            X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig};
+            X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2};
   int rows_per_block = 4 * (64 / lpr);
   int blocks = (int)ceil_div(g->n_nodes, rows_per_block);
   if (transpose) {

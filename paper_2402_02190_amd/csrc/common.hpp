@@ -123,6 +123,8 @@ struct GemmProblem {
   float* bias_grad;  // [M]: also write sum_k op(A)[row, k] (B stored [K, N] only), or null
   float* sig_out;    // [M, N] (ld_sig): also write sigmoid(C), or null
   int64_t ld_sig;
+  const float* add;  // [M, N] (ld_add): added to the result after the bias, or null
+  int64_t ld_add;
 };
 
 // Up to 4 independent problems in one launch, all with the same operand layout.
@@ -132,10 +134,12 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void
                        size_t ws_bytes, hipStream_t stream);
 
 // sig_out (optional) receives sigmoid(Y) with leading dimension ld_sig.
+// add2 (optional) is a second addend [N, width] (ld_add2), applied after add.
 cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
                       float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
                       bool relu, const float* mask, int64_t ld_mask, hipStream_t stream,
-                      float* sig_out = nullptr, int64_t ld_sig = 0);
+                      float* sig_out = nullptr, int64_t ld_sig = 0, const float* add2 = nullptr,
+                      int64_t ld_add2 = 0);
 
 cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t ldp,
                     hipStream_t stream);

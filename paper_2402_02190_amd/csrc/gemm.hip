@@ -58,6 +58,8 @@ struct ProbDev {
   float* bias_grad;  // [M] column sums of op(A) via a virtual ones column of B, or null
   float* sig_out;    // [M, N] (ld_sig): sigmoid of the result, or null
   int64_t ld_sig;
+  const float* add;  // [M, N] (ld_add): extra addend, or null
+  int64_t ld_add;
   int n_eff;         // N + 1 when bias_grad is set
   int tiles_m, tiles_n;
   int64_t part_off;  // float offset of this problem's split-K partials
@@ -151,6 +153,7 @@ struct Tile {
 // C[row, col] = mask(relu(v + beta C)) and optionally sigmoid(C) into sig_out.
 __device__ inline void epilogue_store(const ProbDev& P, int row, int col, float v) {
   float* cp = P.C + (int64_t)row * P.ldc + col;
+  if (P.add) v += P.add[(int64_t)row * P.ld_add + col];
   if (P.beta != 0.f) v += P.beta * *cp;
   if (P.relu) v = fmaxf(v, 0.f);
   if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
@@ -499,6 +502,8 @@ void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs
     d.relu = q.relu;
     d.bias_grad = q.bias_grad;
     d.sig_out = q.sig_out;
+    d.add = q.add;
+    d.ld_add = q.ld_add;
     d.ld_sig = q.ld_sig;
     d.n_eff = n_eff_of(q);
     d.part_off = off;

@@ -38,6 +38,7 @@ struct Layer {
 };
 
 struct Plan {
+  const float* z_offset;  // [N, S] added to the output layer, or null
   int L;
   bool sage, recompute;
   int N;
@@ -106,6 +107,7 @@ void wgrad_problems(const Plan& p, int k, GemmProblem* q) {
 
 void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
   make_layers(cfg, N, p);
+  p->z_offset = cfg->z_offset;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -177,6 +179,10 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       q.relu = last ? 0 : 1;
       q.sig_out = P;
       q.ld_sig = l.out;
+      if (last && p.z_offset) {
+        q.add = p.z_offset;
+        q.ld_add = l.out;
+      }
       CPRA_CHECK(gemm_batch(false, true, &q, 1, nullptr, 0, st));
     } else {
       float* YY = fptr(ws, p.yy_off);
@@ -192,7 +198,7 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       }
       CPRA_CHECK(gemm_batch(false, true, q, 2, nullptr, 0, st));
       CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, b, !last, nullptr,
-                           0, st, P, l.out));
+                           0, st, P, l.out, last ? p.z_offset : nullptr, l.out));
     }
     H = dst;
     ldh = ldd;

@@ -51,7 +51,11 @@ def gamma_schedule(t: int, T: int, g0: float, g1: float) -> float:
 
 
 class CPRASolver:
-    def __init__(self, graph: DeviceGraph, cfg: CPRAConfig, lam=None, device="cuda"):
+    """z_offset (optional): float32 [N, S] device tensor of fixed logits added to the
+    GNN's output (a learned warm start); the solver keeps a reference to it."""
+
+    def __init__(self, graph: DeviceGraph, cfg: CPRAConfig, lam=None, device="cuda",
+                 z_offset: Optional[torch.Tensor] = None):
         if cfg.problem not in ("mis", "maxcut"):
             raise ValueError("problem must be 'mis' or 'maxcut'")
         self.graph = graph
@@ -60,8 +64,12 @@ class CPRASolver:
         N, S = graph.n, cfg.S
         self.problem_id = api.MIS if cfg.problem == "mis" else api.MAXCUT
         in_dim = cfg.hidden if cfg.in_dim is None else cfg.in_dim
+        if z_offset is not None and tuple(z_offset.shape) != (N, S):
+            raise ValueError(f"z_offset must be [{N}, {S}]")
+        self.z_offset = z_offset
         self.model_cfg = api.make_model_cfg(api.SAGE if cfg.layer_kind == "sage" else api.GCN,
-                                            cfg.n_layers, in_dim, cfg.hidden, S, cfg.recompute)
+                                            cfg.n_layers, in_dim, cfg.hidden, S, cfg.recompute,
+                                            z_offset)
         if cfg.problem == "mis":
             if lam is None:
                 raise ValueError("MIS needs a penalty grid lambda [S]")

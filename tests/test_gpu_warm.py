@@ -1,0 +1,256 @@
+"""Parity of the learned warm start (node features, BF16 message-passing network,
+its backward and training step, and the z_offset entry into CPRA) against the
+FP64 oracle, through the C ABI.
+
+Tolerances.  Integer results (triangle counts) and the feature bit patterns
+are compared exactly.  The network computes with bfloat16 operands and FP32
+accumulation; the oracle rounds to bfloat16 at the same points, so the two
+differ only where an FP32-vs-FP64 summation difference (about 1e-7 of the
+value) moves a value across a bfloat16 rounding boundary.  That happens for a
+fraction of roughly 1e-7 / 2^-8 ~ 3e-5 of the values per rounding point and
+changes each such value by one bfloat16 ulp (2^-8 relative), so one rounding
+point contributes about sqrt(3e-5) * 2^-8 ~ 2e-5 to the norm-wise relative
+error.  Sums that nearly cancel raise the flip rate (their FP32 relative
+error is large), and each layer carries the earlier flips forward, so a
+three-layer network measures up to ~4e-4 at its output.  BF16_TOL = 2e-3
+leaves a factor of five.  Where no
+bfloat16 rounding separates the compared values (the output layer's weight
+gradients given the same saved activations, the BCE gradient, the Adam update
+given the same gradients) the FP32 contract of 1e-5 applies.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import TOL, assert_close_array, assert_update_close, need_gpu, say, to_dev
+from oracle import gnn as ognn
+from oracle import objective as oobj
+from oracle import train as otrain
+from oracle import warmstart as W
+from workloads import (csr_from_edges, disjoint_union, erdos_renyi_graph, init_mpnn_params,
+                       init_params, random_channels, random_regular_graph)
+
+pytestmark = pytest.mark.gpu
+
+BF16_TOL = 2e-3
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def api_mod():
+    from paper_2402_02190_amd import api
+    return api
+
+
+def complete_graph(n):
+    u, v = np.triu_indices(n, 1)
+    return csr_from_edges(n, u, v)
+
+
+def bits(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint16)
+
+
+FEATURE_GRAPHS = [
+    ("er300", lambda: erdos_renyi_graph(300, 0.05, 1)),
+    ("rrg1000_d5", lambda: random_regular_graph(1000, 5, 2)),
+    ("rrg2000_d10", lambda: random_regular_graph(2000, 10, 3)),
+    ("complete70", lambda: complete_graph(70)),   # 69 neighbours: more than one pass of 64 lanes
+    ("batch_with_isolated", lambda: disjoint_union([erdos_renyi_graph(50, 0.1, 4), erdos_renyi_graph(6, 0.0, 5),
+                                                   random_regular_graph(40, 3, 6)])),
+]
+
+
+@pytest.mark.parametrize("case", FEATURE_GRAPHS, ids=[c[0] for c in FEATURE_GRAPHS])
+@pytest.mark.parametrize("in_dim,n_rand", [(16, 14), (32, 5)])
+def test_node_features_bit_exact(case, in_dim, n_rand):
+    from paper_2402_02190_amd.warmstart import WarmStartNet
+    api = api_mod()
+    name, gfn = case
+    g = gfn()
+    say(f"features {name} n={g.n} nnz={g.nnz} in_dim={in_dim} n_rand={n_rand}")
+    dg = api.DeviceGraph.from_csr(g)
+    net = WarmStartNet(3, in_dim, 64, 32, n_rand)
+    rand = random_channels(g.n, n_rand, seed=11)
+    feat, tri = net.features(dg, rand, triangles=True)
+    torch.cuda.synchronize()
+    fo, to = W.node_features(g, rand, in_dim)
+    assert np.array_equal(tri.cpu().numpy()[: g.n], to)
+    assert np.array_equal(bits(feat)[: g.n], W.bf16_bits(fo))
+    if name == "complete70":
+        assert np.all(to == 69 * 68 // 2)
+    say(f"  triangles total {int(to.sum())}, features bit-exact")
+
+
+def _mpnn_cases():
+    return [
+        ("L3_in16_h64_s32", lambda: random_regular_graph(1000, 5, 2), 3, 16, 64, 32),
+        ("L2_in32_h32_s64", lambda: erdos_renyi_graph(777, 6.0 / 776, 3), 2, 32, 32, 64),
+        ("L1_in16_s128", lambda: random_regular_graph(500, 3, 4), 1, 16, 32, 128),
+        ("L3_in64_h64_s96_batch", lambda: disjoint_union([random_regular_graph(300, 4, 5),
+                                                          erdos_renyi_graph(9, 0.0, 6),
+                                                          erdos_renyi_graph(401, 0.02, 7)]),
+         3, 64, 64, 96),
+    ]
+
+
+MPNN_CASES = _mpnn_cases()
+
+
+def _setup(case, seed=1):
+    from paper_2402_02190_amd.warmstart import WarmStartNet
+    api = api_mod()
+    name, gfn, L, in_dim, hidden, S = case
+    g = gfn()
+    dg = api.DeviceGraph.from_csr(g)
+    n_rand = in_dim - 2
+    net = WarmStartNet(L, in_dim, hidden, S, n_rand)
+    p = init_mpnn_params(in_dim, hidden, S, L, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    for Ly in p["layers"]:
+        Ly["b"] = (rng.standard_normal(Ly["b"].shape) * 0.1).astype(np.float32)
+    net.load_params(p)
+    rand = random_channels(g.n, n_rand, seed=seed + 2)
+    feat = net.features(dg, rand)
+    fo, _ = W.node_features(g, rand, in_dim)
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    return api, g, dg, net, p, feat, fo, M
+
+
+@pytest.mark.parametrize("case", MPNN_CASES, ids=[c[0] for c in MPNN_CASES])
+def test_mpnn_forward_matches_oracle(case):
+    api, g, dg, net, p, feat, fo, M = _setup(case)
+    say(f"mpnn forward {case[0]} n={g.n}")
+    ws = net.workspace(dg)
+    Zw = net.forward(dg, feat, ws)
+    torch.cuda.synchronize()
+    Zo, cache = W.mpnn_forward(p, fo, M, bf16=True)
+    assert_close_array(Zw.cpu().numpy()[: g.n], Zo, tol=BF16_TOL, what="Z_w")
+    for k in range(net.n_layers):
+        for which, key in ((0, "H"), (1, "A")):
+            if which == 0 and k == 0:
+                continue
+            got = W.from_bf16_bits(api.mpnn_saved(dg, net.cfg, ws, k, which, g.n).cpu().numpy()
+                                   .view(np.uint16))[:, : cache[k][key].shape[1]]
+            ref = cache[k][key]
+            frac = float(np.mean(got != ref))
+            say(f"  layer {k} {key}: {100 * frac:.4f}% of bf16 values differ")
+            # one-ulp flips, mostly on near-cancelling sums; a wrong rounding mode
+            # (e.g. truncation) would flip about half of them
+            assert frac <= 5e-2
+            assert_close_array(got, ref, tol=BF16_TOL, what=f"{key}{k}")
+
+
+@pytest.mark.parametrize("case", MPNN_CASES, ids=[c[0] for c in MPNN_CASES])
+def test_mpnn_backward_matches_oracle_given_saved_activations(case):
+    api, g, dg, net, p, feat, fo, M = _setup(case, seed=3)
+    say(f"mpnn backward {case[0]} n={g.n}")
+    ws = net.workspace(dg)
+    net.forward(dg, feat, ws)
+    dZ = (np.random.default_rng(9).standard_normal((g.n, net.S))).astype(np.float32)
+    grads = torch.zeros_like(net.params)
+    api.mpnn_backward(dg, net.cfg, feat, to_dev(dZ), grads, ws)
+    torch.cuda.synchronize()
+    # the oracle's backward from the device's own saved activations (teacher forcing)
+    cache = []
+    for k in range(net.n_layers):
+        H = fo if k == 0 else W.from_bf16_bits(
+            api.mpnn_saved(dg, net.cfg, ws, k, 0, g.n).cpu().numpy().view(np.uint16))
+        A = W.from_bf16_bits(api.mpnn_saved(dg, net.cfg, ws, k, 1, g.n).cpu().numpy().view(np.uint16))
+        Ly = p["layers"][k]
+        cache.append({"H": H, "A": A, "Ws": W.bf16_round(Ly["Ws"]), "Wn": W.bf16_round(Ly["Wn"])})
+    go = W.mpnn_backward(cache, M, dZ.astype(np.float64), bf16=True)
+    gg = net.unpack(grads)
+    for k in range(net.n_layers):
+        tol = TOL if k == net.n_layers - 1 else BF16_TOL
+        for key in ("Ws", "Wn", "b"):
+            assert_close_array(gg["layers"][k][key], go["layers"][k][key], tol=tol, what=f"d{key}{k}")
+
+
+def test_bce_grad_matches_oracle():
+    api = api_mod()
+    rng = np.random.default_rng(0)
+    n, S = 1237, 48
+    Z = (rng.standard_normal((n, S)) * 4).astype(np.float32)
+    X = (rng.random((n, S)) < 0.3).astype(np.uint8)
+    dZ0 = rng.standard_normal((n, S)).astype(np.float32)
+    dZ = to_dev(dZ0)
+    api.bce_grad(to_dev(Z), torch.from_numpy(X).cuda(), 0.7, dZ)
+    ref = dZ0.astype(np.float64) + W.bce_grad(Z.astype(np.float64), X, 0.7)
+    assert_close_array(dZ.cpu().numpy(), ref, what="dZ + bce")
+
+
+@pytest.mark.parametrize("case", [MPNN_CASES[0], MPNN_CASES[3]], ids=[MPNN_CASES[0][0], MPNN_CASES[3][0]])
+def test_mpnn_train_step_matches_oracle(case):
+    api, g, dg, net, p, feat, fo, M = _setup(case, seed=5)
+    S = net.S
+    lam = np.logspace(-1, 1, S).astype(np.float32)
+    gamma, beta = 0.05, 0.5
+    X = (np.random.default_rng(3).random((g.n, S)) < 0.35).astype(np.uint8)
+    lam_d = to_dev(lam)  # the config holds its device pointer: keep the tensor alive
+    lc = api.make_loss_cfg(api.MIS, S, lam_d, 2, gamma, 0.0, 0, None, gamma, gamma, 2)
+    adam = api.AdamCfg(1e-3, 0.9, 0.999, 1e-8, 0.0)
+    cfg = api.make_mpnn_step_cfg(net.cfg, lc, adam, beta)
+    ws = torch.empty(api.mpnn_train_step_workspace_bytes(dg, cfg), dtype=torch.uint8, device="cuda")
+    Zw = torch.zeros((g.n, S), dtype=torch.float32, device="cuda")
+    dZw = torch.zeros_like(Zw)
+    terms = torch.zeros((dg.n_graphs, S + 2), dtype=torch.float64, device="cuda")
+    target = torch.from_numpy(X).cuda()
+    before = net.params.cpu().numpy().copy()
+    api.mpnn_train_step(dg, cfg, net.params, net.grads, net.m, net.v, feat, target, Zw, dZw, terms,
+                        ws, t=1)
+    torch.cuda.synchronize()
+    Zo, terms_o, dZo, go = W.warm_loss_and_grads(p, fo, M, g, "mis", lam.astype(np.float64), gamma,
+                                                 X, beta, bf16=True)
+    assert_close_array(Zw.cpu().numpy(), Zo, tol=BF16_TOL, what="Z_w")
+    assert_close_array(dZw.cpu().numpy(), dZo, tol=BF16_TOL, what="dZ_w")
+    gg = net.unpack(net.grads)
+    for k in range(net.n_layers):
+        for key in ("Ws", "Wn", "b"):
+            assert_close_array(gg["layers"][k][key], go["layers"][k][key], tol=BF16_TOL,
+                               what=f"d{key}{k}")
+    T = terms.cpu().numpy()
+    for gi, to in enumerate(terms_o):
+        scale = np.abs(to["head"]).sum() + abs(gamma) * to["entropy"] + 1.0
+        assert abs(T[gi, :S].sum() - to["head"].sum()) <= BF16_TOL * scale
+    # Adam applied to the device's own gradients (no bf16 rounding in between)
+    g_flat = net.grads.cpu().numpy().astype(np.float64)
+    ref = before.astype(np.float64).copy()
+    otrain.adam_update(ref, g_flat, np.zeros_like(ref), np.zeros_like(ref), 1, 1e-3)
+    assert_update_close(net.params.cpu().numpy(), before, ref, what="params after Adam")
+
+
+@pytest.mark.parametrize("S,hidden", [(10, 32), (64, 32)], ids=["lf_last_layer", "af_last_layer"])
+def test_cpra_with_z_offset_matches_oracle(S, hidden):
+    api = api_mod()
+    from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
+    g = random_regular_graph(300, 3, 8)
+    dg = api.DeviceGraph.from_csr(g)
+    off = (np.random.default_rng(4).standard_normal((g.n, S)) * 2).astype(np.float32)
+    off_d = to_dev(off)
+    lam = np.linspace(0.5, 5, S).astype(np.float32)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=hidden, S=S)
+    sol = CPRASolver(dg, cfg, lam, z_offset=off_d)
+    p = init_params("gcn", g.n, 2, hidden, S, seed=5)
+    sol.load_params(p)
+    sol.step()
+    torch.cuda.synchronize()
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    ocfg = otrain.StepConfig(problem="mis", lam=lam.astype(np.float64))
+    gamma = otrain.gamma_at(0, cfg.T, cfg.gamma_start, cfg.gamma_end)
+    Zo, terms, dZo, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, gamma, z_offset=off)
+    assert_close_array(sol.Z.cpu().numpy(), Zo, what="Z with offset")
+    assert_close_array(sol.dZ.cpu().numpy(), dZo, what="dZ with offset")
+    gg = sol.unpack(sol.grads)
+    assert_close_array(gg["emb"], go["emb"], what="d emb")
+    # the offset is what was added: without it the logits differ by exactly it
+    sol2 = CPRASolver(dg, cfg, lam)
+    sol2.load_params(p)
+    sol2.forward()
+    torch.cuda.synchronize()
+    Zplain, _ = ognn.forward(ognn.to_f64(p), M)
+    assert_close_array(sol2.Z.cpu().numpy(), Zplain, what="Z without offset")
