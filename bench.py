@@ -144,6 +144,90 @@ def cpu_baseline(pr, g, params, seconds: float):
                       f"of the same workload; median step time"}
 
 
+def loss_sweep(sizes, S: int = 64, d: int = 20, reps: int = 10):
+    """The fused loss kernel (A P gather + objective + dZ) and the mean-aggregation
+    SpMM alone over near-d-regular random graphs of growing N (the 100,000-node,
+    20-regular, S = 64 workload and larger), timed by the library profiler: the
+    compulsory-byte rate against HBM peak, and the neighbour-gather rate, which
+    is what the kernel actually streams (4 nnz S bytes, cache-resident below
+    the 256 MB Infinity Cache, from HBM above it)."""
+    import torch
+    from paper_2402_02190_amd import api
+    from workloads import random_permutation_graph
+    rows = []
+    for n in sizes:
+        t0 = time.time()
+        g = random_permutation_graph(n, d, seed=1000 + n % 997)
+        dg = api.DeviceGraph.from_csr(g, validate=False)
+        log(f"[sweep] n={n} nnz={g.nnz} ({time.time() - t0:.1f}s to generate)")
+        lam = torch.from_numpy(np.logspace(-1, 1, S).astype(np.float32)).cuda()
+        lc = api.make_loss_cfg(api.MIS, S, lam, 2, 0.05, 0.0, 0, None, 0.05, 0.05, 2)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(n)
+        Z = torch.randn((n, S), device="cuda", generator=gen) * 2.0
+        P = torch.empty_like(Z)
+        api.sigmoid(Z, P)
+        dZ = torch.empty_like(Z)
+        Y = torch.empty_like(Z)
+        ws = torch.empty(api.loss_workspace_bytes(dg, lc), dtype=torch.uint8, device="cuda")
+        for _ in range(2):  # warm-up
+            api.loss_fwd_bwd(dg, lc, Z, dZ, None, ws, P=P)
+            api.aggregate_mean(dg, P, Y)
+        torch.cuda.synchronize()
+        torch.cuda._sleep(int(2.4e9 * 0.002 * reps))
+        api.profile_begin()
+        for _ in range(reps):
+            api.loss_fwd_bwd(dg, lc, Z, dZ, None, ws, P=P)
+        for _ in range(reps):
+            api.aggregate_mean(dg, P, Y)
+        api.profile_stop()
+        torch.cuda.synchronize()
+        st = api.profile_end()
+        row = {"n": n, "nnz": g.nnz, "S": S}
+        gather = 4.0 * g.nnz * S
+        for name in ("loss_fwd_bwd", "aggregate"):
+            la, ms, _, by = st[name]
+            t = ms / 1e3 / la
+            row[name] = {"avg_us": t * 1e6, "compulsory_bytes": by / la,
+                         "compulsory_GBps": by / la / t / 1e9,
+                         "frac_hbm_peak": by / la / t / 1e9 / PEAK_HBM_GBS,
+                         "gather_bytes": gather, "gather_GBps": gather / t / 1e9}
+        log(f"[sweep] n={n}: loss {row['loss_fwd_bwd']['avg_us']:.1f} us "
+            f"({row['loss_fwd_bwd']['compulsory_GBps']:.0f} GB/s compulsory, "
+            f"{row['loss_fwd_bwd']['gather_GBps']:.0f} GB/s gathered); aggregate "
+            f"{row['aggregate']['avg_us']:.1f} us ({row['aggregate']['compulsory_GBps']:.0f} GB/s, "
+            f"{row['aggregate']['gather_GBps']:.0f} GB/s gathered)")
+        rows.append(row)
+        del Z, P, dZ, Y, ws, dg
+        torch.cuda.empty_cache()
+    return rows
+
+
+WARM_WEIGHTS = os.path.join(ROOT, "paper_2402_02190_amd", "weights", "warmstart_mis_rrg.npz")
+
+
+def time_to_target(seeds=(0, 1), n: int = 50_000, d: int = 5):
+    """The second half of the metric on the 50,000-node warm-start workload: wall
+    time until the best feasible head (decoded every 50 steps) reaches a fraction
+    of the plain method's final MIS size, for the plain cold-start run, the
+    warm-started run (learned network, committed weights) and the same short
+    schedule without the network."""
+    from paper_2402_02190_amd.warmstart_train import evaluate
+    if not os.path.exists(WARM_WEIGHTS):
+        return None
+    s = evaluate(WARM_WEIGHTS, n=n, degrees=(d,), seeds=seeds, T=3000, K=50,
+                 warm_gamma_start=-0.5, warm_T=1000, decay_steps=500)
+    return {"workload": f"C5: random {d}-regular N={n}, MIS, S=32, GCN 2x64, seeds {list(seeds)}",
+            "target": "plain (cold-start) CPRA's final best feasible MIS size after 3000 steps",
+            "plain": "gamma -2 -> 0.1 over 3000 steps",
+            "warm": "z_offset = learned BF16 network output, fading to 0 over 500 steps; "
+                    "gamma -0.5 -> 0.1 over 1000 steps (inference time included)",
+            "control": "the warm arm's schedule without the network",
+            "median_seconds_to_fraction": s["curves"],
+            "final_over_target": {"warm": s["mean_warm_final_over_target"],
+                                  "control": s["mean_control_final_over_target"]}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,12 +239,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-time-to-target", action="store_true")
     ap.add_argument("--tuning-file", default=None,
                     help="GEMM tuning table: loaded if it exists, else written after autotuning "
                          "(default: the committed MI355X table of the workload, if any)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run only the short sequence the HBM counter passes profile")
+    ap.add_argument("--loss-sweep", type=int, nargs="*", default=None, metavar="N",
+                    help="instead of the step benchmark: time the fused loss kernel and the "
+                         "aggregation alone on near-20-regular graphs of these sizes, S = 64")
     args = ap.parse_args()
+    if args.loss_sweep is not None:
+        sizes = args.loss_sweep or [100_000, 400_000, 1_000_000, 4_000_000]
+        rows = loss_sweep(sizes)
+        print(json.dumps({"sweep": "loss_fwd_bwd and aggregate, near-20-regular random graphs, S=64",
+                          "peak_hbm_GBps": PEAK_HBM_GBS, "rows": rows}), flush=True)
+        return
     if args.tuning_file is None and not args.no_autotune:
         args.tuning_file = default_tuning_file(args.workload)
     if args.gpus != 1:
@@ -260,6 +354,13 @@ def main():
         for k, v in kernels.items():
             log(f"[bench]   {k:28s} {v['launches']:5d} launches {v['avg_us']:9.2f} us avg "
                 f"{100 * v['share']:5.1f}%")
+
+    if rank == 0 and not args.no_time_to_target:
+        log("[bench] time to target: cold vs warm start on the 50,000-node graph ...")
+        ttt = time_to_target()
+        if ttt is not None:
+            result["time_to_target"] = ttt
+            log(f"[bench] time to target: {json.dumps(ttt['median_seconds_to_fraction'])}")
 
     if rank == 0 and not args.no_cpu_baseline:
         log(f"[bench] timing the FP64 oracle for up to {args.cpu_seconds:.0f}s ...")

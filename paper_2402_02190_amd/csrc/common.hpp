@@ -120,7 +120,7 @@ struct GemmProblem {
   int64_t ld_mask;
   float beta;
   int relu;
-  float* bias_grad;  // [M]: also write sum_k op(A)[row, k] (B stored [K, N] only), or null
+  float* bias_grad;  // [M]: also write sum_k op(A)[row, k], or null
   float* sig_out;    // [M, N] (ld_sig): also write sigmoid(C), or null
   int64_t ld_sig;
   const float* add;  // [M, N] (ld_add): added to the result after the bias, or null

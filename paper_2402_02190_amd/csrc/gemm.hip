@@ -18,9 +18,10 @@
 // copy.  Split-K writes FP32 partial tiles that a second kernel sums in a
 // fixed order (deterministic), applying the epilogue.
 //
-// Weight-gradient problems may ask for the column sums of A as well (the bias
-// gradient sum_k dY[k, :]): B then gets one virtual extra column of ones,
-// whose output column is written to `bias_grad` instead of C.
+// Weight-gradient problems may ask for the row sums of op(A) as well (the bias
+// gradient sum_k dY[k, :]): the blocks of the first column tile add up the A
+// tiles they stage in LDS (VALU adds beside the MFMAs, fixed order), so no
+// extra output column of tiles is computed.
 //
 // Tile shape and split count come from a table filled by the autotuner
 // (timed candidates per problem shape) or, for untuned shapes, a heuristic.
@@ -55,7 +56,7 @@ struct ProbDev {
   int64_t ld_mask;
   float beta;
   int relu;
-  float* bias_grad;  // [M] column sums of op(A) via a virtual ones column of B, or null
+  float* bias_grad;  // [M] row sums of op(A) over K (computed by the first column tile), or null
   float* sig_out;    // [M, N] (ld_sig): sigmoid of the result, or null
   int64_t ld_sig;
   const float* add;  // [M, N] (ld_add): extra addend, or null
@@ -82,9 +83,8 @@ struct Tile {
   static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
   float4 reg[NV];
 
-  // ones_col >= mn_lim: that (virtual) column reads as 1 for every valid k.
   __device__ inline void load(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim, int k0,
-                              int k_lim, bool vec_ok, int tid, int ones_col) {
+                              int k_lim, bool vec_ok, int tid) {
     const bool full = vec_ok && (mn0 + R <= mn_lim) && (k0 + BK <= k_lim);
     if (full) {
 #pragma unroll
@@ -121,11 +121,10 @@ struct Tile {
         const int gk = k0 + k, gm = mn0 + rq;
         const bool kok = gk < k_lim;
         const float* p = X + (int64_t)(kok ? gk : 0) * ld;
-        const float one = kok ? 1.f : 0.f;
-        reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : (gm + 0 == ones_col ? one : 0.f);
-        reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : (gm + 1 == ones_col ? one : 0.f);
-        reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : (gm + 2 == ones_col ? one : 0.f);
-        reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : (gm + 3 == ones_col ? one : 0.f);
+        reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : 0.f;
+        reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : 0.f;
+        reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : 0.f;
+        reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : 0.f;
       }
     }
   }
@@ -228,14 +227,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
 
   TA ta;
   TB tb;
-  const int ones_col = P.bias_grad ? P.N : -1;
   auto load = [&](int kt) {
     const int pc = kt < nt0 ? 0 : 1;
     const int k0 = (kt - (pc ? nt0 : 0)) * BK;
-    ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid, -1);
-    tb.load(P.B[pc], P.ldb[pc], n0, P.N, k0, P.K[pc], P.vecB[pc] != 0 && ones_col < 0, tid,
-            ones_col);
+    ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid);
+    tb.load(P.B[pc], P.ldb[pc], n0, P.N, k0, P.K[pc], P.vecB[pc] != 0, tid);
   };
+  // Bias gradient (row sums of op(A) over this block's K range): the blocks of
+  // the first column tile add up the staged A tile with plain VALU adds, thread
+  // t owning row t % BM and a fixed slice of each tile's BK rows (zero padding
+  // outside the matrix is already in the tile).
+  constexpr int BG = NT / BM > 0 ? NT / BM : 1;  // threads per row
+  static_assert(BK % BG == 0, "bias slice");
+  const bool do_bias = P.bias_grad != nullptr && tn_idx == 0;
+  const int b_row = tid % BM, b_grp = tid / BM;
+  float bsum = 0.f;
 
   if (kt_begin < kt_end) {
     load(kt_begin);
@@ -248,6 +254,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
       if (more) load(kt + 1);
       const float* as = As[cur];
       const float* bs = Bs[cur];
+      if (do_bias && b_grp < BG) {
+#pragma unroll
+        for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
+      }
       float af[BK / 2][TM], bf[BK / 2][TN];
 #pragma unroll
       for (int kk = 0; kk < BK / 2; ++kk) {
@@ -281,9 +291,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int col = n0 + (wn * TN + j) * 32 + l32;
-      if (col >= P.n_eff) continue;
-      const bool virt = col == P.N;  // the bias-gradient column
-      const float bv = (!partial && !virt && P.bias) ? P.bias[col] : 0.f;
+      if (col >= P.N) continue;
+      const float bv = (!partial && P.bias) ? P.bias[col] : 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + (wm * TM + i) * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
@@ -291,12 +300,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
         const float v = acc[i][j][r];
         if (partial) {
           part[(int64_t)row * P.n_eff + col] = v;
-        } else if (virt) {
-          P.bias_grad[row] = v;
         } else {
           epilogue_store(P, row, col, v + bv);
         }
       }
+    }
+  }
+  if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
+    float* red = As[0];
+    if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
+    __syncthreads();
+    if (tid < BM && m0 + tid < P.M) {
+      float v = 0.f;
+      for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
+      if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
+      else P.bias_grad[m0 + tid] = v;
     }
   }
 }
@@ -353,6 +371,8 @@ struct Plan {
 };
 
 inline int n_eff_of(const GemmProblem& q) { return q.N + (q.bias_grad ? 1 : 0); }
+// columns covered by output tiles: N (at least one tile when only the bias gradient is wanted)
+inline int tile_cols_of(const GemmProblem& q) { return q.N > 0 ? q.N : (q.bias_grad ? 1 : 0); }
 
 int total_k_tiles(const GemmProblem& q, int bk) {
   int kt = (int)ceil_div(q.piece[0].K, bk);
@@ -362,7 +382,7 @@ int total_k_tiles(const GemmProblem& q, int bk) {
 
 int64_t tiles_of(const GemmProblem* probs, int n, const Cfg& c) {
   int64_t t = 0;
-  for (int i = 0; i < n; ++i) t += ceil_div(probs[i].M, c.bm) * ceil_div(n_eff_of(probs[i]), c.bn);
+  for (int i = 0; i < n; ++i) t += ceil_div(probs[i].M, c.bm) * ceil_div(tile_cols_of(probs[i]), c.bn);
   return t;
 }
 
@@ -435,7 +455,7 @@ void launch_cfg(LaunchArgs& args, hipStream_t stream) {
   int max_tiles = 0;
   for (int i = 0; i < args.n_prob; ++i) {
     args.p[i].tiles_m = (int)ceil_div(args.p[i].M, BM);
-    args.p[i].tiles_n = (int)ceil_div(args.p[i].n_eff, BN);
+    args.p[i].tiles_n = (int)ceil_div(args.p[i].N > 0 ? args.p[i].N : (args.p[i].bias_grad ? 1 : 0), BN);
     max_tiles = max(max_tiles, args.p[i].tiles_m * args.p[i].tiles_n);
   }
   dim3 grid;
@@ -517,9 +537,9 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
   fill_args(probs, n, pl.splits, ws, &args);
   double flops = 0, red_bytes = 0;
   for (int i = 0; i < n; ++i) {
-    const double mn = (double)args.p[i].M * args.p[i].n_eff;
+    const double mn = (double)args.p[i].M * args.p[i].N;
     flops += 2.0 * mn * ((double)args.p[i].K[0] + (args.p[i].n_pieces > 1 ? args.p[i].K[1] : 0));
-    red_bytes += 4.0 * mn * (pl.splits + 1);
+    red_bytes += 4.0 * (double)args.p[i].M * args.p[i].n_eff * (pl.splits + 1);
   }
   // profiler family = one kernel instantiation: layout + tile configuration
   static const char* layout[2][2] = {{"nn", "nt"}, {"tn", "tt"}};
@@ -618,8 +638,8 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void
                        size_t ws_bytes, hipStream_t stream) {
   if (n < 1 || n > kMaxProblems) CPRA_FAIL(CPRA_ERR_PARAM, "gemm: 1..4 problems per launch");
   for (int i = 0; i < n; ++i)
-    if (probs[i].bias_grad && (b_t || probs[i].bias))
-      CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad needs B stored [K, N] and no bias");
+    if (probs[i].bias_grad && probs[i].bias)
+      CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad and bias are exclusive");
   int live = 0;
   for (int i = 0; i < n; ++i)
     if (probs[i].M > 0 && n_eff_of(probs[i]) > 0) ++live;

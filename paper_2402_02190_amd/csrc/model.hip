@@ -13,8 +13,8 @@
 //    dH = G_s + M^T G_n (masked by H > 0 in the same pass);
 //  * linear-first: T = M^T dY, dWs = dY^T H, dWn = T^T H,
 //    dH = [dY | T] [Ws; Wn] (masked in the GEMM epilogue).
-// db = column sums of dY, produced by the dWs GEMM through a virtual ones
-// column (no separate pass).  The output layer also writes P = sigmoid(Z) in
+// db = column sums of dY, added up by the dWs GEMM from the dY tiles it stages
+// in LDS (no separate pass).  The output layer also writes P = sigmoid(Z) in
 // its epilogue, for the loss.  M^T = A D^-1 is applied by the transposed
 // aggregation (not M: the graph need not be regular).  With recompute set,
 // AX is not kept from the forward and is rebuilt in the backward.

@@ -11,6 +11,7 @@ from .graphs import (  # noqa: F401
     CSRGraph,
     csr_from_edges,
     random_regular_graph,
+    random_permutation_graph,
     erdos_renyi_graph,
     disjoint_union,
     induced_subgraph,

@@ -113,6 +113,36 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray,
     return CSRGraph(n, row_ptr.astype(np.int32), dst.astype(np.int32), weight)
 
 
+def random_permutation_graph(n: int, d: int, seed: int) -> CSRGraph:
+    """Near-d-regular random graph for very large n (d even): the union of d/2
+    uniformly random permutations, each contributing the edges {i, pi(i)}, with
+    self-loops and repeated edges dropped (an O(d^2 / n) fraction of each node's
+    edges in expectation).  Fully vectorised, so graphs of millions of nodes take
+    seconds; used for size sweeps where the exact-regular generator is too slow."""
+    if d % 2:
+        raise ValueError("d must be even")
+    rng = np.random.default_rng(seed)
+    us, vs = [], []
+    for _ in range(d // 2):
+        pi = rng.permutation(n)
+        us.append(np.arange(n, dtype=np.int64))
+        vs.append(pi.astype(np.int64))
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    keep = u != v
+    a = np.minimum(u[keep], v[keep])
+    b = np.maximum(u[keep], v[keep])
+    key = np.unique(a * n + b)
+    lo, hi = key // n, key % n
+    both = np.sort(np.concatenate([lo * n + hi, hi * n + lo]))  # (row, col) order
+    src, dst = both // n, both % n
+    if src.size >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 indexing")
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    return CSRGraph(n, row_ptr.astype(np.int32), dst.astype(np.int32), None)
+
+
 def random_regular_graph(n: int, d: int, seed: int) -> CSRGraph:
     """Uniform-ish random d-regular simple graph on n nodes (pairing + switchings)."""
     if d < 0 or d >= n or (n * d) % 2:
