@@ -166,7 +166,10 @@ __device__ inline void epilogue_store(const ProbDev& P, int row, int col, float 
 
 // A_T: A stored [K, M] (M contiguous); otherwise [M, K].
 // B_T: B stored [N, K] (K contiguous); otherwise [K, N].
-template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T>
+// PF: prefetch distance in K tiles (1: the next tile is loaded while the
+// current one is multiplied; 2: two tiles ahead, in two register sets, so a
+// load has two K steps of MFMA work to land).
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / (32 * WM);  // 32x32 accumulators per wave along M
@@ -225,9 +228,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  TA ta;
-  TB tb;
-  auto load = [&](int kt) {
+  auto load_into = [&](TA& ta, TB& tb, int kt) {
     const int pc = kt < nt0 ? 0 : 1;
     const int k0 = (kt - (pc ? nt0 : 0)) * BK;
     ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid);
@@ -243,42 +244,78 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   const int b_row = tid % BM, b_grp = tid / BM;
   float bsum = 0.f;
 
-  if (kt_begin < kt_end) {
-    load(kt_begin);
-    ta.store(As[0], tid);
-    tb.store(Bs[0], tid);
-    __syncthreads();
-    for (int kt = kt_begin; kt < kt_end; ++kt) {
-      const int cur = (kt - kt_begin) & 1;
-      const bool more = kt + 1 < kt_end;
-      if (more) load(kt + 1);
-      const float* as = As[cur];
-      const float* bs = Bs[cur];
-      if (do_bias && b_grp < BG) {
+  // multiply the tile staged in LDS buffer `cur` (and add its A rows for the bias)
+  auto compute = [&](int cur) {
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+    if (do_bias && b_grp < BG) {
 #pragma unroll
-        for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
+      for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
+    }
+    float af[BK / 2][TM], bf[BK / 2][TN];
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kr = 2 * kk + half;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
+  };
+
+  if constexpr (PF == 1) {
+    TA ta;
+    TB tb;
+    if (kt_begin < kt_end) {
+      load_into(ta, tb, kt_begin);
+      ta.store(As[0], tid);
+      tb.store(Bs[0], tid);
+      __syncthreads();
+      for (int kt = kt_begin; kt < kt_end; ++kt) {
+        const int cur = (kt - kt_begin) & 1;
+        const bool more = kt + 1 < kt_end;
+        if (more) load_into(ta, tb, kt + 1);
+        compute(cur);
+        if (more) {
+          ta.store(As[cur ^ 1], tid);
+          tb.store(Bs[cur ^ 1], tid);
+        }
+        __syncthreads();
       }
-      float af[BK / 2][TM], bf[BK / 2][TN];
-#pragma unroll
-      for (int kk = 0; kk < BK / 2; ++kk) {
-        const int kr = 2 * kk + half;
-#pragma unroll
-        for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
-      }
-#pragma unroll
-      for (int kk = 0; kk < BK / 2; ++kk)
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
-      if (more) {
-        ta.store(As[cur ^ 1], tid);
-        tb.store(Bs[cur ^ 1], tid);
+    }
+  } else {
+    // Two register sets; the loop is unrolled by two so that every set is
+    // named statically.  In the body for tile kt: LDS[cur] holds tile kt, set
+    // `nxt` holds tile kt + 1 (stored to LDS[cur ^ 1] at the end), and set
+    // `fre` (whose tile kt is already in LDS) receives tile kt + 2.
+    TA ta0, ta1;
+    TB tb0, tb1;
+    auto body = [&](int kt, int cur, TA& fre_a, TB& fre_b, TA& nxt_a, TB& nxt_b) {
+      if (kt + 2 < kt_end) load_into(fre_a, fre_b, kt + 2);
+      compute(cur);
+      if (kt + 1 < kt_end) {
+        nxt_a.store(As[cur ^ 1], tid);
+        nxt_b.store(Bs[cur ^ 1], tid);
       }
       __syncthreads();
+    };
+    if (kt_begin < kt_end) {
+      load_into(ta0, tb0, kt_begin);
+      ta0.store(As[0], tid);
+      tb0.store(Bs[0], tid);
+      if (kt_begin + 1 < kt_end) load_into(ta1, tb1, kt_begin + 1);
+      __syncthreads();
+      for (int kt = kt_begin; kt < kt_end; kt += 2) {
+        body(kt, 0, ta0, tb0, ta1, tb1);
+        if (kt + 1 < kt_end) body(kt + 1, 1, ta1, tb1, ta0, tb0);
+      }
     }
   }
 
@@ -320,15 +357,41 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
 }
 
 // Sum split-K partials in split order and apply the epilogue.
-__global__ void k_gemm_splitk_reduce(LaunchArgs args) {
+// Sum split-K partials and apply the epilogue.  A block covers 64 consecutive
+// outputs with 4 groups of 64 threads; group g adds the g-th quarter of the
+// splits in split order (loads issued eight at a time so their latencies
+// overlap), and the four group sums are added in group order: a fixed order,
+// so the result is deterministic.
+constexpr int kRedElems = 64, kRedGroups = 4;
+__global__ __launch_bounds__(kRedElems * kRedGroups) void k_gemm_splitk_reduce(LaunchArgs args) {
+  __shared__ float red[kRedGroups][kRedElems];
   const int prob = blockIdx.y;
   const ProbDev& P = args.p[prob];
   const int64_t total = (int64_t)P.M * P.n_eff;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
+  const int e = threadIdx.x % kRedElems, grp = threadIdx.x / kRedElems;
+  const int64_t idx = (int64_t)blockIdx.x * kRedElems + e;
+  if ((int64_t)blockIdx.x * kRedElems >= total) return;  // uniform per block
   const float* part = args.partial + P.part_off;
+  const int per = (args.splits + kRedGroups - 1) / kRedGroups;
+  const int s0 = min(args.splits, grp * per), s1 = min(args.splits, s0 + per);
   float v = 0.f;
-  for (int s = 0; s < args.splits; ++s) v += part[(int64_t)s * total + idx];
+  if (idx < total) {
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(s + u) * total + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; s < s1; ++s) v += part[(int64_t)s * total + idx];
+  }
+  red[grp][e] = v;
+  __syncthreads();
+  if (grp != 0 || idx >= total) return;
+  v = red[0][e];
+#pragma unroll
+  for (int g2 = 1; g2 < kRedGroups; ++g2) v += red[g2][e];
   const int row = (int)(idx / P.n_eff);
   const int col = (int)(idx - (int64_t)row * P.n_eff);
   if (col == P.N) {
@@ -358,13 +421,29 @@ constexpr Cfg kCfgs[] = {
     {128, 128, 16, 2, 2},  // 7
     {32, 64, 32, 1, 1},    // 8: 64 threads, 32x64 per wave
     {64, 32, 32, 1, 1},    // 9: 64 threads, 64x32 per wave
+    // prefetch distance 2 (tiles loaded two K steps ahead)
+    {64, 64, 16, 2, 2},    // 10
+    {64, 64, 32, 2, 2},    // 11
+    {128, 64, 16, 2, 2},   // 12
+    {64, 128, 16, 2, 2},   // 13
+    {128, 128, 16, 2, 2},  // 14
+    // prefetch distance 2 with more than one accumulator per wave (fewer, busier waves)
+    {64, 32, 16, 1, 1},    // 15: 64 threads, 64x32 per wave
+    {32, 64, 16, 1, 1},    // 16: 64 threads, 32x64 per wave
+    {64, 64, 16, 1, 1},    // 17: 64 threads, 64x64 per wave
+    {64, 64, 16, 2, 1},    // 18: 128 threads, 32x64 per wave
+    {128, 64, 16, 2, 1},   // 19: 128 threads, 64x64 per wave
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 const char* kCfgNames[kNumCfgs] = {"64x64x32_w2x2",   "64x64x32_w2x1", "64x64x32_w1x1",
                                    "128x64x32_w2x2",  "64x128x32_w2x2", "128x128x32_w2x2",
                                    "64x64x16_w2x2",   "128x128x16_w2x2", "32x64x32_w1x1",
-                                   "64x32x32_w1x1"};
+                                   "64x32x32_w1x1",   "64x64x16_w2x2_p2", "64x64x32_w2x2_p2",
+                                   "128x64x16_w2x2_p2", "64x128x16_w2x2_p2",
+                                   "128x128x16_w2x2_p2", "64x32x16_w1x1_p2",
+                                   "32x64x16_w1x1_p2", "64x64x16_w1x1_p2",
+                                   "64x64x16_w2x1_p2", "128x64x16_w2x1_p2"};
 
 struct Plan {
   int cfg, splits;
@@ -393,13 +472,15 @@ int max_k_tiles(const GemmProblem* probs, int n, int bk) {
 }
 
 // Split count that brings the launch to ~512 blocks, keeping >= 4 K steps per split.
+constexpr int kMaxSplits = 256;
+
 int heuristic_splits(const GemmProblem* probs, int n, const Cfg& c) {
   const int64_t tiles = tiles_of(probs, n, c);
   const int mkt = max_k_tiles(probs, n, c.bk);
   if (tiles >= 512 || mkt < 8) return 1;
   int s = (int)ceil_div(512, tiles);
   s = min(s, max(1, mkt / 4));
-  return max(1, min(s, 64));
+  return max(1, min(s, kMaxSplits));
 }
 
 Plan heuristic_plan(const GemmProblem* probs, int n, bool can_split) {
@@ -450,7 +531,7 @@ bool lookup(const std::string& key, Plan* out) {
 }
 
 // ---- launching ---------------------------------------------------------------
-template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T>
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF>
 void launch_cfg(LaunchArgs& args, hipStream_t stream) {
   int max_tiles = 0;
   for (int i = 0; i < args.n_prob; ++i) {
@@ -467,25 +548,35 @@ void launch_cfg(LaunchArgs& args, hipStream_t stream) {
     const int64_t groups = (int64_t)args.n_prob * args.splits;
     grid = dim3((unsigned)(ceil_div(groups, 8) * 8 * max_tiles));
   }
-  hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T>), grid, dim3(64 * WM * WN), 0, stream,
-                     args);
+  hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T, PF>), grid, dim3(64 * WM * WN), 0,
+                     stream, args);
 }
 
 template <bool A_T, bool B_T>
 void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
   switch (cfg) {
-#define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN) \
-  case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T>(args, stream); break;
-    CPRA_GEMM_CFG(0, 64, 64, 32, 2, 2)
-    CPRA_GEMM_CFG(1, 64, 64, 32, 2, 1)
-    CPRA_GEMM_CFG(2, 64, 64, 32, 1, 1)
-    CPRA_GEMM_CFG(3, 128, 64, 32, 2, 2)
-    CPRA_GEMM_CFG(4, 64, 128, 32, 2, 2)
-    CPRA_GEMM_CFG(5, 128, 128, 32, 2, 2)
-    CPRA_GEMM_CFG(6, 64, 64, 16, 2, 2)
-    CPRA_GEMM_CFG(7, 128, 128, 16, 2, 2)
-    CPRA_GEMM_CFG(8, 32, 64, 32, 1, 1)
-    CPRA_GEMM_CFG(9, 64, 32, 32, 1, 1)
+#define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
+  case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF>(args, stream); break;
+    CPRA_GEMM_CFG(0, 64, 64, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(1, 64, 64, 32, 2, 1, 1)
+    CPRA_GEMM_CFG(2, 64, 64, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(3, 128, 64, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(4, 64, 128, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(5, 128, 128, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(6, 64, 64, 16, 2, 2, 1)
+    CPRA_GEMM_CFG(7, 128, 128, 16, 2, 2, 1)
+    CPRA_GEMM_CFG(8, 32, 64, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(9, 64, 32, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(10, 64, 64, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(11, 64, 64, 32, 2, 2, 2)
+    CPRA_GEMM_CFG(12, 128, 64, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(13, 64, 128, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(14, 128, 128, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(15, 64, 32, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(16, 32, 64, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(17, 64, 64, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(18, 64, 64, 16, 2, 1, 2)
+    CPRA_GEMM_CFG(19, 128, 64, 16, 2, 1, 2)
 #undef CPRA_GEMM_CFG
     default: break;
   }
@@ -558,8 +649,8 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
     for (int i = 0; i < n; ++i) maxel = max(maxel, (int64_t)args.p[i].M * args.p[i].n_eff);
     {
       ProfScope ps("gemm_splitk_reduce", stream, 0.0, red_bytes);
-      hipLaunchKernelGGL(k_gemm_splitk_reduce, dim3(ceil_div(maxel, 256), n), dim3(256), 0, stream,
-                         args);
+      hipLaunchKernelGGL(k_gemm_splitk_reduce, dim3(ceil_div(maxel, kRedElems), n),
+                         dim3(kRedElems * kRedGroups), 0, stream, args);
     }
     CPRA_CHECK_LAUNCH("gemm_splitk_reduce");
   }
@@ -584,7 +675,7 @@ cpra_status tune(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws, 
     const int h = heuristic_splits(probs, n, kCfgs[c]);
     if (ws != nullptr && h > 1) {
       for (int s : {h / 2, h, 2 * h})
-        if (s > 1 && s <= 64 && partial_floats(s, probs, n) * sizeof(float) <= ws_bytes &&
+        if (s > 1 && s <= kMaxSplits && partial_floats(s, probs, n) * sizeof(float) <= ws_bytes &&
             s != splits.back())
           splits.push_back(s);
     }
@@ -628,7 +719,7 @@ size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, 
   size_t best = 0;
   for (int c = 0; c < kNumCfgs; ++c) {
     const int h = heuristic_splits(probs, n, kCfgs[c]);
-    const int s = h > 1 ? min(64, 2 * h) : 1;
+    const int s = h > 1 ? min(kMaxSplits, 2 * h) : 1;
     if (s > 1) best = std::max(best, partial_floats(s, probs, n) * sizeof(float));
   }
   return best;
@@ -752,7 +843,7 @@ cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, int32_t* cfg
 cpra_status cpra_autotune_set(const char* key, int32_t cfg, int32_t splits) {
   using namespace cpra;
   if (key == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "autotune_set: key is NULL");
-  if (cfg < 0 || cfg >= kNumCfgs || splits < 1 || splits > 64)
+  if (cfg < 0 || cfg >= kNumCfgs || splits < 1 || splits > kMaxSplits)
     CPRA_FAIL(CPRA_ERR_PARAM, "autotune_set: config %d / splits %d out of range", cfg, splits);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_table.find(key) == g_table.end()) g_order.push_back(key);

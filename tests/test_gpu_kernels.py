@@ -331,3 +331,36 @@ def test_round_eval_bit_exact(gname, S, problem):
         else:
             assert np.array_equal(val[gi * S:(gi + 1) * S], e["cut_edges"])
             np.testing.assert_allclose(wv[gi * S:(gi + 1) * S], e["cut"], rtol=1e-12)
+
+
+N_GEMM_CFGS = 20  # tile configurations the library's tuner chooses from
+
+
+@pytest.mark.parametrize("cfg", range(N_GEMM_CFGS))
+def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
+    """Each tile configuration, forced through the tuning table, in every operand
+    layout, with and without split-K, on a ragged shape (M, N, K not multiples
+    of any tile) with bias and ReLU."""
+    a = api()
+    rng = np.random.default_rng(cfg)
+    M, N, K = 333, 130, 77
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    bias = rng.standard_normal(N).astype(np.float32)
+    try:
+        for ta in (False, True):
+            for tb in (False, True):
+                for splits in (1, 3, 40):
+                    key = f"{'T' if ta else 'N'}{'T' if tb else 'N'}|{M}x{N}x{K}"
+                    a.autotune_reset()
+                    a.autotune_set(key, cfg, splits)
+                    A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+                    B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+                    C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+                    a.gemm(to_dev(A), to_dev(B), C, ta, tb, bias=to_dev(bias), relu=True, ws=ws)
+                    torch.cuda.synchronize()
+                    ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
+                    ref = np.maximum(ref + bias, 0.0)
+                    assert_close_array(C.cpu().numpy(), ref, 2e-6,
+                                       f"cfg {cfg} {key} splits {splits}")
+    finally:
+        a.autotune_reset()

@@ -234,3 +234,42 @@ def test_c1_end_to_end_against_oracle_and_exact_optimum():
     assert best_gpu <= alpha_g and best_gpu >= 0.9 * alpha_g
     assert np.all(ev["violations"][0][pr.lam > 1.0] == 0)
     assert agree >= 0.9
+
+
+@pytest.mark.parametrize("cfg", range(20))
+def test_sage_bias_gradient_under_every_weight_gradient_plan(cfg):
+    """The bias gradient is summed inside the weight-gradient GEMM by the first
+    column tile: check db (and dWs) of a 2-layer SAGE model with every tile
+    configuration forced on those GEMMs, with and without split-K."""
+    api, CPRAConfig, CPRASolver = mods()
+    g = random_regular_graph(700, 5, 9)
+    dg = api.DeviceGraph.from_csr(g)
+    cfgc = CPRAConfig(problem="mis", layer_kind="sage", n_layers=2, hidden=64, S=32)
+    lam = np.logspace(-1, 1, 32).astype(np.float32)
+    p = init_params("sage", g.n, 2, 64, 32, seed=4)
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    ocfg = otrain.StepConfig(problem="mis", lam=lam.astype(np.float64))
+    _, _, _, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, cfgc.gamma_start)
+    # find the weight-gradient problem keys from one tuned step
+    sol = CPRASolver(dg, cfgc, lam)
+    sol.load_params(p)
+    table = sol.autotune()
+    tn_keys = [e[0] for e in table if e[0].startswith("TN")]
+    assert tn_keys
+    try:
+        for splits in (1, 4, 150):
+            api.autotune_reset()
+            for k in tn_keys:
+                api.autotune_set(k, cfg, splits)
+            sol.load_params(p)
+            sol.step()
+            torch.cuda.synchronize()
+            gg = sol.unpack(sol.grads)
+            for k in range(2):
+                assert_close_array(gg["layers"][k]["b"], go["layers"][k]["b"],
+                                   what=f"cfg {cfg} splits {splits} db{k}")
+                assert_close_array(gg["layers"][k]["Ws"], go["layers"][k]["Ws"],
+                                   what=f"cfg {cfg} splits {splits} dWs{k}")
+    finally:
+        api.autotune_reset()
+        sol.close()
