@@ -42,13 +42,16 @@ def dscore(X: np.ndarray) -> float:
     return 2.0 * pairwise_hamming_sum(X) / (N * S * (S - 1))
 
 
-def evaluate_one(X: np.ndarray, graph, problem: str) -> Dict[str, object]:
+def evaluate_one(X: np.ndarray, graph, problem: str, node_weight=None) -> Dict[str, object]:
+    """node_weight ([N] or [N, S], MIS only): also the total weight of each head's set."""
     ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
     Xi = X.astype(np.int64)
     out = {"pair_hamming": pairwise_hamming_sum(X)}
     if problem == "mis":
         out["size"] = Xi.sum(axis=0)
         out["violations"] = (Xi[ei] * Xi[ej]).sum(axis=0)
+        from .objective import node_weights
+        out["weight"] = (node_weights(node_weight, *X.shape) * Xi).sum(axis=0)
     elif problem == "maxcut":
         differ = (Xi[ei] != Xi[ej])
         out["cut_edges"] = differ.sum(axis=0).astype(np.int64)
@@ -58,14 +61,15 @@ def evaluate_one(X: np.ndarray, graph, problem: str) -> Dict[str, object]:
     return out
 
 
-def evaluate(X: np.ndarray, graph, problem: str):
+def evaluate(X: np.ndarray, graph, problem: str, node_weight=None):
     """Per-graph evaluation; a single graph gives a one-element list."""
     from .objective import _slice_graph
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     res = []
     for g in range(gp.size - 1):
         sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
-        res.append(evaluate_one(X[gp[g]:gp[g + 1]], sub, problem))
+        nw = None if node_weight is None else np.asarray(node_weight)[gp[g]:gp[g + 1]]
+        res.append(evaluate_one(X[gp[g]:gp[g + 1]], sub, problem, nw))
     return res
 
 

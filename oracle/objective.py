@@ -5,7 +5,9 @@ Notation follows the paper: P in [0,1]^{N x S} holds S relaxed solutions
 appendix, sigmoid after the last layer).
 
 Discrete objectives (problem-specification appendix, objective table):
-  MIS:    l(x; G, lam) = -sum_i x_i + lam * sum_{(i,j) in E} x_i x_j
+  MIS:    l(x; G, lam) = -sum_i w_i x_i + lam * sum_{(i,j) in E} x_i x_j
+          (node weights w_i = 1 for plain MIS; weighted MIS takes one weight
+          vector per head -- the weighted-MIS tasks of the two-stage appendix)
   MaxCut: l(x; G)      = sum_{i<j} A_ij (2 x_i x_j - x_i - x_j)
 Each edge {i, j} is counted once (i < j).  The relaxation (Sec. 2.2) keeps
 the same multilinear polynomial with p in [0,1]^N, so it equals the
@@ -60,10 +62,23 @@ def edges_of(row_ptr: np.ndarray, col_idx: np.ndarray, weight: Optional[np.ndarr
 # Discrete objectives (objective table)
 # ---------------------------------------------------------------------------
 
-def discrete_mis(x: np.ndarray, ei, ej, w, lam: float) -> float:
-    """-sum_i x_i + lam * sum_{(i,j) in E} A_ij x_i x_j for one binary vector."""
+def discrete_mis(x: np.ndarray, ei, ej, w, lam: float, node_w=None) -> float:
+    """-sum_i w_i x_i + lam * sum_{(i,j) in E} A_ij x_i x_j for one binary vector."""
     x = np.asarray(x, dtype=np.float64)
-    return float(-x.sum() + lam * np.sum(w * x[ei] * x[ej]))
+    lin = x.sum() if node_w is None else float(np.sum(np.asarray(node_w, dtype=np.float64) * x))
+    return float(-lin + lam * np.sum(w * x[ei] * x[ej]))
+
+
+def node_weights(node_weight, N: int, S: int) -> np.ndarray:
+    """Node weights as [N, S] float64: None -> ones; [N] -> shared by every head."""
+    if node_weight is None:
+        return np.ones((N, S))
+    w = np.asarray(node_weight, dtype=np.float64)
+    if w.ndim == 1:
+        w = np.repeat(w[:, None], S, axis=1)
+    if w.shape != (N, S):
+        raise ValueError("node weights must be [N] or [N, S]")
+    return w
 
 
 def discrete_maxcut(x: np.ndarray, ei, ej, w) -> float:
@@ -77,13 +92,14 @@ def discrete_maxcut(x: np.ndarray, ei, ej, w) -> float:
 # ---------------------------------------------------------------------------
 
 def relaxed_head_losses(P: np.ndarray, ei, ej, w, problem: str,
-                        lam: Optional[np.ndarray]) -> np.ndarray:
+                        lam: Optional[np.ndarray], node_weight=None) -> np.ndarray:
     """l_hat(P[:, s]; C, lam_s) for every head s (the relaxation of Sec. 2.2)."""
     P = np.asarray(P, dtype=np.float64)
     if problem == "mis":
         lam = np.asarray(lam, dtype=np.float64)
         pair = np.sum(w[:, None] * P[ei] * P[ej], axis=0)
-        return -P.sum(axis=0) + lam * pair
+        nw = node_weights(node_weight, *P.shape)
+        return -(nw * P).sum(axis=0) + lam * pair
     if problem == "maxcut":
         return np.sum(w[:, None] * (2.0 * P[ei] * P[ej] - P[ei] - P[ej]), axis=0)
     raise ValueError(problem)
@@ -128,7 +144,7 @@ def diversity_term(P: np.ndarray, ddof: int = 0) -> float:
 # ---------------------------------------------------------------------------
 
 def loss_terms(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
-               nu: float = 0.0, ddof: int = 0) -> Dict[str, object]:
+               nu: float = 0.0, ddof: int = 0, node_weight=None) -> Dict[str, object]:
     """All loss terms of one graph at logits Z [N, S].
 
     Returns {"head": l_hat_s [S], "entropy": S(P), "psi": Psi(P), "total": R}.
@@ -136,7 +152,7 @@ def loss_terms(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int
     """
     ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
     P, Q = sigmoid_pair(Z)
-    head = relaxed_head_losses(P, ei, ej, w, problem, lam)
+    head = relaxed_head_losses(P, ei, ej, w, problem, lam, node_weight)
     ent = entropy_term(P, Q, alpha)
     psi = diversity_term(P, ddof) if P.shape[1] > 1 else 0.0
     total = float(head.sum() + gamma * ent + nu * psi)
@@ -144,10 +160,10 @@ def loss_terms(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int
 
 
 def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: float,
-               alpha: int, nu: float = 0.0, ddof: int = 0) -> np.ndarray:
+               alpha: int, nu: float = 0.0, ddof: int = 0, node_weight=None) -> np.ndarray:
     """dR/dP [N, S] (derived by hand from the loss above).
 
-    problem part: MIS    -1 + lam_s * sum_{j in N(i)} A_ij P_js
+    problem part: MIS    -w_is + lam_s * sum_{j in N(i)} A_ij P_js
                   MaxCut sum_{j in N(i)} A_ij (2 P_js - 1)
     annealing:    gamma * d/dP (1 - (2P-1)^alpha) = -2 alpha gamma (2P-1)^(alpha-1)
     diversity:    nu * dPsi/dP_is = -nu * S (P_is - mu_i) / ((S - ddof) sigma_i),
@@ -160,7 +176,7 @@ def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: fl
     np.add.at(nb, ei, w[:, None] * P[ej])
     np.add.at(nb, ej, w[:, None] * P[ei])
     if problem == "mis":
-        g = -1.0 + np.asarray(lam, dtype=np.float64)[None, :] * nb
+        g = -node_weights(node_weight, N, S) + np.asarray(lam, dtype=np.float64)[None, :] * nb
     elif problem == "maxcut":
         wdeg = np.zeros(N, dtype=np.float64)
         np.add.at(wdeg, ei, w)
@@ -182,19 +198,21 @@ def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: fl
 
 
 def grad_wrt_Z(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
-               nu: float = 0.0, ddof: int = 0) -> np.ndarray:
+               nu: float = 0.0, ddof: int = 0, node_weight=None) -> np.ndarray:
     """dR/dZ = dR/dP * P * (1 - P), with 1 - P taken as sigmoid(-Z)."""
     P, Q = sigmoid_pair(Z)
-    return grad_wrt_P(P, Q, graph, problem, lam, gamma, alpha, nu, ddof) * P * Q
+    return grad_wrt_P(P, Q, graph, problem, lam, gamma, alpha, nu, ddof, node_weight) * P * Q
 
 
-def batched_loss_terms(Z: np.ndarray, graph, problem, lam, gamma, alpha, nu=0.0, ddof=0):
+def batched_loss_terms(Z: np.ndarray, graph, problem, lam, gamma, alpha, nu=0.0, ddof=0,
+                       node_weight=None):
     """Per-graph loss terms of a block-diagonal batch (graph.graph_ptr slices)."""
     out = []
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     for g in range(gp.size - 1):
         sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
-        out.append(loss_terms(Z[gp[g]:gp[g + 1]], sub, problem, lam, gamma, alpha, nu, ddof))
+        nw = None if node_weight is None else np.asarray(node_weight)[gp[g]:gp[g + 1]]
+        out.append(loss_terms(Z[gp[g]:gp[g + 1]], sub, problem, lam, gamma, alpha, nu, ddof, nw))
     return out
 
 

@@ -65,6 +65,7 @@ class StepConfig:
     beta2: float = 0.999
     eps: float = 1e-8
     weight_decay: float = 0.0
+    node_weight: Optional[np.ndarray] = None  # MIS node weights [N] or [N, S]; None = 1
 
 
 def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=None,
@@ -75,19 +76,22 @@ def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=
     ``z_offset``: optional warm-start logits added to the output (see gnn.forward)."""
     Z, cache = gnn.forward(params, M, z_offset)
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
+    nw = cfg.node_weight
     if gp.size > 2:
         terms = objective.batched_loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
-                                             cfg.nu, cfg.ddof)
+                                             cfg.nu, cfg.ddof, nw)
         dZ = np.zeros_like(Z)
         for g in range(gp.size - 1):
             sub = objective._slice_graph(graph, int(gp[g]), int(gp[g + 1]))
+            nwg = None if nw is None else np.asarray(nw)[gp[g]:gp[g + 1]]
             dZ[gp[g]:gp[g + 1]] = objective.grad_wrt_Z(Z[gp[g]:gp[g + 1]], sub, cfg.problem,
-                                                       cfg.lam, gamma, cfg.alpha, cfg.nu, cfg.ddof)
+                                                       cfg.lam, gamma, cfg.alpha, cfg.nu, cfg.ddof,
+                                                       nwg)
     else:
         terms = [objective.loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
-                                      cfg.nu, cfg.ddof)]
+                                      cfg.nu, cfg.ddof, nw)]
         dZ = objective.grad_wrt_Z(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha, cfg.nu,
-                                  cfg.ddof)
+                                  cfg.ddof, nw)
     grads = gnn.backward(params, M, cache, dZ, relu_active)
     if return_cache:
         return Z, terms, dZ, grads, cache
