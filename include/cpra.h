@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 2
+#define CPRA_ABI_VERSION 4
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -134,7 +134,9 @@ cpra_status cpra_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, in
  * objective table of the problem-specification appendix):
  *   P = sigmoid(Z),
  *   R = sum_s l_s(P[:,s]) + gamma * sum_{i,s} (1 - (2 P_is - 1)^alpha) + nu * Psi(P),
- *   MIS:    l_s = -sum_i P_is + lambda_s * sum_{i<j} A_ij P_is P_js
+ *   MIS:    l_s = -sum_i w_is P_is + lambda_s * sum_{i<j} A_ij P_is P_js
+ *           (w = 1 unless node weights are given: weighted MIS, one weight
+ *           vector per head for the multi-task form of the two-stage appendix)
  *   MaxCut: l_s = sum_{i<j} A_ij (2 P_is P_js - P_is - P_js)
  *   Psi    = -S * sum_i STD_s[P_is]  (population STD, or sample STD if std_ddof = 1)
  * Output dZ = dR/dZ and, per graph g of the batch, terms[g*(S+2) + c]:
@@ -156,6 +158,11 @@ typedef struct {
   const int32_t* step_counter;
   float gamma_start, gamma_end;
   int32_t T;
+  /* Optional MIS node weights (device): w_is = node_weight[i * ld_node_weight + s],
+   * or node_weight[i] for every head when ld_node_weight = 0.  NULL: w = 1.
+   * CPRA_ERR_PARAM for MaxCut. */
+  const float* node_weight;
+  int64_t ld_node_weight;
 } cpra_loss_cfg;
 
 size_t cpra_loss_workspace_bytes(const cpra_csr* g, const cpra_loss_cfg* cfg);
@@ -195,6 +202,19 @@ typedef struct {
    * learned warm start (cpra_mpnn_forward) enters CPRA; the backward is
    * unchanged (dZ/d offset = 1, the offset is not trained).  NULL: none. */
   const float* z_offset;
+  /* Frozen encoder (the two-stage scheme of Sec. 3.1's last paragraph and the
+   * two-stage appendix): layers below train_from_layer, and the embedding when
+   * train_from_layer > 0, are not trained -- the backward writes gradients only
+   * for layers >= train_from_layer (the others are left untouched) and does not
+   * propagate below that layer; cpra_train_step's Adam updates only the
+   * trainable tail of the parameter vector.  0: everything is trained. */
+  int32_t train_from_layer;
+  /* 1: the forward starts at layer train_from_layer (>= 1) from the input that
+   * the previous forward on the same workspace saved -- valid because the
+   * layers below are frozen (and, unless recompute is set, that layer's saved
+   * neighbour aggregate is reused too).  The caller guarantees that such a
+   * forward ran on this workspace with the same frozen parameters. */
+  int32_t reuse_frozen_prefix;
 } cpra_model_cfg;
 
 /* Total float count including the embedding; -1 on invalid config. */
@@ -269,7 +289,8 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
  * Rounding and evaluation (training-setting appendix: P <= 0.5 -> 0,
  * P > 0.5 -> 1, evaluated exactly as Z > 0; objective table; Sec. 4.1
  * Evaluation Metrics; Proposition 3.2).  Per graph g and head s:
- *   MIS:    value = |{i : x_is = 1}|,  violations = |{i<j in E : x_is = x_js = 1}|
+ *   MIS:    value = |{i : x_is = 1}|,  violations = |{i<j in E : x_is = x_js = 1}|,
+ *           wvalue = sum_i w_is x_is (node weights as in cpra_loss_cfg; 1 if NULL)
  *   MaxCut: value = |{i<j in E : x_is != x_js}| (cut edges), violations = 0,
  *           wvalue = sum of A_ij over cut edges (FP64, fixed-order sums)
  *   pair_hamming[g] = sum_{s<l} d_H(x_s, x_l) = sum_i k_i (S - k_i), k_i = sum_s x_is.
@@ -281,6 +302,7 @@ size_t cpra_round_eval_workspace_bytes(const cpra_csr* g, int32_t S);
 cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const float* Z,
                             int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
                             int64_t* violations, double* wvalue, int64_t* pair_hamming,
+                            const float* node_weight, int64_t ld_node_weight,
                             void* ws, size_t ws_bytes, cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------

@@ -36,13 +36,15 @@ class LossCfg(C.Structure):
     _fields_ = [("problem", C.c_int32), ("S", C.c_int32), ("alpha", C.c_int32),
                 ("std_ddof", C.c_int32), ("gamma", C.c_float), ("nu", C.c_float),
                 ("lambda_", C.c_void_p), ("step_counter", C.c_void_p),
-                ("gamma_start", C.c_float), ("gamma_end", C.c_float), ("T", C.c_int32)]
+                ("gamma_start", C.c_float), ("gamma_end", C.c_float), ("T", C.c_int32),
+                ("node_weight", C.c_void_p), ("ld_node_weight", C.c_int64)]
 
 
 class ModelCfg(C.Structure):
     _fields_ = [("layer_kind", C.c_int32), ("n_layers", C.c_int32), ("in_dim", C.c_int32),
                 ("hidden", C.c_int32), ("S", C.c_int32), ("recompute", C.c_int32),
-                ("z_offset", C.c_void_p)]
+                ("z_offset", C.c_void_p), ("train_from_layer", C.c_int32),
+                ("reuse_frozen_prefix", C.c_int32)]
 
 
 class AdamCfg(C.Structure):
@@ -93,7 +95,7 @@ PROTOTYPES = {
     "cpra_train_step_workspace_bytes": (SZ, [PCsr, PStep]),
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),
     "cpra_round_eval_workspace_bytes": (SZ, [PCsr, I32]),
-    "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, SZ, P]),
+    "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, I64, P, SZ, P]),
     "cpra_node_features": (None, [PCsr, I32, I32, P, I64, P, I64, P, P]),
     "cpra_mpnn_param_count": (I64, [PMpnn]),
     "cpra_mpnn_param_offsets": (None, [PMpnn, C.POINTER(I64)]),

@@ -126,12 +126,26 @@ def gemm(A: torch.Tensor, B: torch.Tensor, C_out: torch.Tensor, trans_a=False, t
     return C_out
 
 
+def _node_weight_args(node_weight: Optional[torch.Tensor]):
+    """(pointer, leading dimension) of MIS node weights: [N] (ld 0) or [N, S]."""
+    if node_weight is None:
+        return None, 0
+    _dev_f32(node_weight, "node_weight")
+    if node_weight.dim() == 1:
+        return node_weight.data_ptr(), 0
+    return node_weight.data_ptr(), node_weight.stride(0)
+
+
 def make_loss_cfg(problem: int, S: int, lam: Optional[torch.Tensor], alpha: int = 2,
                   gamma: float = 0.0, nu: float = 0.0, std_ddof: int = 0,
                   step_counter: Optional[torch.Tensor] = None, gamma_start: float = 0.0,
-                  gamma_end: float = 0.0, T: int = 1) -> LossCfg:
+                  gamma_end: float = 0.0, T: int = 1,
+                  node_weight: Optional[torch.Tensor] = None) -> LossCfg:
+    """node_weight: optional MIS node weights, float32 [N] or [N, S] on the device
+    (the caller keeps the tensors alive while the config is used)."""
+    nw, ld = _node_weight_args(node_weight)
     return LossCfg(problem, S, alpha, std_ddof, gamma, nu, _ptr(lam), _ptr(step_counter),
-                   gamma_start, gamma_end, T)
+                   gamma_start, gamma_end, T, nw, ld)
 
 
 def loss_workspace_bytes(g, cfg: LossCfg) -> int:
@@ -153,15 +167,18 @@ def sigmoid(Z: torch.Tensor, P: torch.Tensor, stream=None):
 
 
 def make_model_cfg(layer_kind: int, n_layers: int, in_dim: int, hidden: int, S: int,
-                   recompute: bool = False, z_offset: torch.Tensor = None) -> ModelCfg:
+                   recompute: bool = False, z_offset: torch.Tensor = None,
+                   train_from_layer: int = 0, reuse_frozen_prefix: bool = False) -> ModelCfg:
     """z_offset: optional float32 [N, S] contiguous device tensor of fixed logits added to
-    the output (the warm start); the caller keeps it alive while the config is used."""
+    the output (the warm start); the caller keeps it alive while the config is used.
+    train_from_layer / reuse_frozen_prefix: a frozen encoder (see include/cpra.h)."""
     if z_offset is not None:
         if z_offset.dtype != torch.float32 or not z_offset.is_contiguous() or z_offset.dim() != 2 \
                 or z_offset.shape[1] != S:
             raise ValueError("z_offset must be a contiguous float32 [N, S] tensor")
     return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute),
-                    None if z_offset is None else z_offset.data_ptr())
+                    None if z_offset is None else z_offset.data_ptr(), int(train_from_layer),
+                    int(reuse_frozen_prefix))
 
 
 def model_param_count(cfg: ModelCfg, n_nodes: int) -> int:
@@ -228,13 +245,14 @@ def round_eval_workspace_bytes(g, S: int) -> int:
 
 
 def round_eval(g, problem: int, Z: torch.Tensor, X=None, value=None, violations=None,
-               wvalue=None, pair_hamming=None, ws=None, stream=None):
+               wvalue=None, pair_hamming=None, ws=None, stream=None, node_weight=None):
     S = Z.shape[1]
     if ws is None:
         ws = torch.empty(round_eval_workspace_bytes(g, S), dtype=torch.uint8, device=Z.device)
+    nw, ld = _node_weight_args(node_weight)
     call("cpra_round_eval", _csr(g), problem, S, _ptr(Z), Z.stride(0), _ptr(X),
          0 if X is None else X.stride(0), _ptr(value), _ptr(violations), _ptr(wvalue),
-         _ptr(pair_hamming), _ptr(ws), ws.numel(), _stream(stream))
+         _ptr(pair_hamming), nw, ld, _ptr(ws), ws.numel(), _stream(stream))
 
 
 # ---------------------------------------------------------------- warm start

@@ -5,9 +5,9 @@
 // Same lane layout as the loss kernel: 64/LPR nodes per wavefront, the LPR
 // lanes of a node cover its heads.  Each edge {i, j} is visited from its
 // smaller endpoint only.  Integer counts are summed per block and added with
-// 64-bit integer atomics (exact, so order does not matter); weighted cut
-// values go through per-item FP64 partials and the fixed-order segmented
-// reduction.
+// 64-bit integer atomics (exact, so order does not matter); weighted values
+// (the cut weight of MaxCut, the set weight of weighted MIS) go through
+// per-item FP64 partials and the fixed-order segmented reduction.
 #include "common.hpp"
 
 namespace cpra {
@@ -32,6 +32,8 @@ struct EvalArgs {
   const int32_t* graph_ptr;
   const int32_t* item_ptr;
   int R;
+  const float* node_w;  // MIS node weights or null (weight 1)
+  int64_t ld_nw;        // 0: one weight per node
 };
 
 template <typename T>
@@ -78,7 +80,14 @@ __global__ __launch_bounds__(256) void k_round_eval(EvalArgs a) {
     if (active) {
       if (mis) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) c_val[c] += x[c];
+        for (int c = 0; c < NC; ++c) {
+          const int s = c * lpr + cl;
+          c_val[c] += x[c];
+          if (x[c] && s < S)
+            c_w[c] += a.node_w ? (double)a.node_w[a.ld_nw ? (int64_t)row * a.ld_nw + s
+                                                            : (int64_t)row]
+                               : 1.0;
+        }
       }
       const int beg = a.row_ptr[row], end = a.row_ptr[row + 1];
       for (int k = beg; k < end; ++k) {
@@ -181,7 +190,8 @@ size_t cpra_round_eval_workspace_bytes(const cpra_csr* g, int32_t S) {
 
 cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const float* Z,
                             int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
-                            int64_t* violations, double* wvalue, int64_t* pair_hamming, void* ws,
+                            int64_t* violations, double* wvalue, int64_t* pair_hamming,
+                            const float* node_weight, int64_t ld_node_weight, void* ws,
                             size_t ws_bytes, cpra_stream_t stream) {
   using namespace cpra;
   CPRA_CHECK(check_csr(g, "round_eval", false, false));
@@ -190,6 +200,10 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
   if (S < 1 || S > 1024) CPRA_FAIL(CPRA_ERR_PARAM, "round_eval: S = %d outside 1..1024", S);
   if (g->n_nodes > 0 && Z == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "round_eval: Z is NULL");
   if (ldz < S || (X && ldx < S)) CPRA_FAIL(CPRA_ERR_SHAPE, "round_eval: leading dimension < S");
+  if (node_weight && problem != CPRA_MIS)
+    CPRA_FAIL(CPRA_ERR_PARAM, "round_eval: node weights are defined for MIS only");
+  if (node_weight && ld_node_weight != 0 && ld_node_weight < S)
+    CPRA_FAIL(CPRA_ERR_SHAPE, "round_eval: ld_node_weight must be 0 or >= S");
   size_t item_off, part_off;
   size_t need = eval_ws(g, S, &item_off, &part_off);
   if (ws == nullptr || ws_bytes < need)
@@ -224,6 +238,8 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
   a.graph_ptr = g->n_graphs > 1 ? g->graph_ptr : nullptr;
   a.item_ptr = item_ptr;
   a.R = G.R;
+  a.node_w = node_weight;
+  a.ld_nw = ld_node_weight;
   const int blocks = (int)G.items_cap;
   ProfScope ps("round_eval", st, 0.0,
                4.0 * (double)g->n_nodes * S + (X ? (double)g->n_nodes * S : 0.0) +

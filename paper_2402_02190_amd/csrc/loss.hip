@@ -2,7 +2,8 @@
 // table of the problem-specification appendix).
 //
 // For node i and head s with P = sigmoid(Z) and (AP)_is = sum_{j in N(i)} A_ij P_js:
-//   MIS:    l_is = P_is (-1 + lambda_s/2 (AP)_is),   dl/dP_is = -1 + lambda_s (AP)_is
+//   MIS:    l_is = P_is (-w_is + lambda_s/2 (AP)_is), dl/dP_is = -w_is + lambda_s (AP)_is
+//           (node weights w, 1 by default)
 //   MaxCut: l_is = P_is ((AP)_is - wdeg_i),          dl/dP_is = 2 (AP)_is - wdeg_i
 // so that sum_i l_is equals the per-head objective with every edge counted once.
 //   annealing: phi_is = 1 - t^alpha, t = 2P - 1 = P - Q (Q = sigmoid(-Z)),
@@ -48,6 +49,8 @@ struct LossArgs {
   int R;
   float* part;
   int64_t items_cap;
+  const float* node_w;  // MIS node weights or null
+  int64_t ld_nw;        // 0: one weight per node
 };
 
 __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
@@ -183,8 +186,10 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
       const float t_am1 = t * tp;  // t^(alpha-1)
       float l, gr;
       if (mis) {
-        l = p[c] * (-1.0f + 0.5f * lam_h[c] * ap[c]);
-        gr = -1.0f + lam_h[c] * ap[c];
+        const float u = a.node_w ? -a.node_w[a.ld_nw ? (int64_t)row * a.ld_nw + s : (int64_t)row]
+                                 : -1.0f;
+        l = p[c] * (u + 0.5f * lam_h[c] * ap[c]);
+        gr = u + lam_h[c] * ap[c];
       } else {
         l = p[c] * (ap[c] - wd);
         gr = 2.0f * ap[c] - wd;
@@ -288,6 +293,10 @@ cpra_status check_loss_cfg(const cpra_csr* g, const cpra_loss_cfg* cfg) {
     CPRA_FAIL(CPRA_ERR_PARAM, "loss: bad device schedule (gamma endpoints finite, T >= 1)");
   if (cfg->problem == CPRA_MIS && g->n_nodes > 0 && cfg->lambda == nullptr)
     CPRA_FAIL(CPRA_ERR_NULL, "loss: lambda is NULL for MIS");
+  if (cfg->node_weight && cfg->problem != CPRA_MIS)
+    CPRA_FAIL(CPRA_ERR_PARAM, "loss: node weights are defined for MIS only");
+  if (cfg->node_weight && cfg->ld_node_weight != 0 && cfg->ld_node_weight < cfg->S)
+    CPRA_FAIL(CPRA_ERR_SHAPE, "loss: ld_node_weight must be 0 or >= S");
   return CPRA_OK;
 }
 
@@ -348,11 +357,15 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.R = G.R;
   a.part = part;
   a.items_cap = G.items_cap;
+  a.node_w = cfg->node_weight;
+  a.ld_nw = cfg->ld_node_weight;
   const int blocks = (int)G.items_cap;
   // compulsory bytes: Z and P read once, dZ written, CSR (+weights), wdeg, partials
   const double ns4 = 4.0 * (double)g->n_nodes * S;
   const double loss_bytes = ns4 * (dZ ? 3.0 : 2.0) + 4.0 * (double)g->nnz * (g->weight ? 2.0 : 1.0) +
                             4.0 * (double)g->n_nodes * (cfg->problem == CPRA_MAXCUT ? 2.0 : 1.0) +
+                            (cfg->node_weight ? 4.0 * (double)g->n_nodes *
+                                                    (cfg->ld_node_weight ? S : 1) : 0.0) +
                             4.0 * (double)(S + 2) * G.items_cap;
   ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes);
   switch (G.nc) {

@@ -39,6 +39,8 @@ struct Layer {
 
 struct Plan {
   const float* z_offset;  // [N, S] added to the output layer, or null
+  int train_from;         // first trained layer (0: all, embedding included)
+  bool reuse_prefix;      // forward starts at train_from from saved activations
   int L;
   bool sage, recompute;
   int N;
@@ -58,6 +60,11 @@ cpra_status check_model_cfg(const cpra_model_cfg* cfg) {
     CPRA_FAIL(CPRA_ERR_PARAM, "model: unknown layer kind %d", cfg->layer_kind);
   if (cfg->n_layers < 1 || cfg->n_layers > kMaxLayers)
     CPRA_FAIL(CPRA_ERR_PARAM, "model: n_layers = %d outside 1..%d", cfg->n_layers, kMaxLayers);
+  if (cfg->train_from_layer < 0 || cfg->train_from_layer >= cfg->n_layers)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: train_from_layer = %d outside 0..%d", cfg->train_from_layer,
+              cfg->n_layers - 1);
+  if (cfg->reuse_frozen_prefix && cfg->train_from_layer < 1)
+    CPRA_FAIL(CPRA_ERR_PARAM, "model: reuse_frozen_prefix needs train_from_layer >= 1");
   if (cfg->in_dim < 1 || cfg->hidden < 1 || cfg->S < 1 || cfg->S > 1024)
     CPRA_FAIL(CPRA_ERR_PARAM, "model: widths must be >= 1 and S <= 1024");
   if (cfg->in_dim > 4096 || cfg->hidden > 4096)
@@ -108,6 +115,8 @@ void wgrad_problems(const Plan& p, int k, GemmProblem* q) {
 void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
   make_layers(cfg, N, p);
   p->z_offset = cfg->z_offset;
+  p->train_from = cfg->train_from_layer;
+  p->reuse_prefix = cfg->reuse_frozen_prefix != 0;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -153,9 +162,12 @@ inline float* fptr(void* ws, size_t off) {
 cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, float* Z,
                          int64_t ldz, void* ws, hipStream_t st) {
   const int N = g->n_nodes;
-  const float* H = params;  // embedding
-  int64_t ldh = p.layer[0].in;
-  for (int k = 0; k < p.L; ++k) {
+  // With a reused frozen prefix the forward starts at the first trained layer,
+  // from the input the previous forward saved.
+  const int k0 = p.reuse_prefix ? p.train_from : 0;
+  const float* H = k0 == 0 ? params : fptr(ws, p.h_off[k0]);  // embedding or saved input
+  int64_t ldh = p.layer[k0].in;
+  for (int k = k0; k < p.L; ++k) {
     const Layer& l = p.layer[k];
     const bool last = k == p.L - 1;
     float* dst = last ? Z : fptr(ws, p.h_off[k + 1]);
@@ -166,7 +178,9 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
     float* P = last ? fptr(ws, p.p_off) : nullptr;  // sigmoid(Z) for the loss
     if (!l.lf) {
       float* AX = fptr(ws, p.recompute ? p.ax_scratch_off : p.ax_off[k]);
-      CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
+      const bool saved_ax = p.reuse_prefix && k == k0 && !p.recompute;  // M H of a frozen input
+      if (!saved_ax)
+        CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
       GemmProblem q{};
       q.piece[0] = GemmPiece{H, Ws, ldh, l.in, l.in};
       q.piece[1] = GemmPiece{AX, Wn, l.in, l.in, l.in};
@@ -241,8 +255,10 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
   int64_t lddy = lddz;
   int ping = 0;
   void* gemm_ws = p.gemm_bytes ? static_cast<char*>(ws) + p.gemm_off : nullptr;
-  for (int k = p.L - 1; k >= 0; --k) {
+  for (int k = p.L - 1; k >= p.train_from; --k) {
     const Layer& l = p.layer[k];
+    // the input gradient is needed unless every layer below (and the embedding) is frozen
+    const bool need_dx = k > p.train_from || p.train_from == 0;
     const float* Hk = (k == 0) ? params : fptr(ws, p.h_off[k]);
     const int64_t ldh = l.in;
     const float* Ws = params + l.off_ws;
@@ -272,6 +288,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
+      if (!need_dx) break;
       GemmProblem r{};
       r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
       r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
@@ -308,6 +325,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
+      if (!need_dx) break;
       float* G = fptr(ws, p.g_off);
       const int64_t ldg = 2 * l.in;
       GemmProblem r[2] = {};
@@ -471,8 +489,10 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   }
   CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side));
   if (side) CPRA_CHECK(join_from(side, st));
-  CPRA_CHECK(adam_step(p.n_params, params, grads, m, v, &cfg->adam, t, step_counter, st,
-                       /*t_offset=*/0));
+  // only the trainable tail [first trained layer, end) when the encoder is frozen
+  const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : 0;
+  CPRA_CHECK(adam_step(p.n_params - a0, params + a0, grads + a0, m + a0, v + a0, &cfg->adam, t,
+                       step_counter, st, /*t_offset=*/0));
   return CPRA_OK;
 }
 

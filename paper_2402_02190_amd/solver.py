@@ -41,6 +41,7 @@ class CPRAConfig:
     eps: float = 1e-8
     weight_decay: float = 0.0
     recompute: bool = False
+    train_from_layer: int = 0  # > 0: layers below (and the embedding) are frozen
 
 
 def gamma_schedule(t: int, T: int, g0: float, g1: float) -> float:
@@ -55,7 +56,8 @@ class CPRASolver:
     GNN's output (a learned warm start); the solver keeps a reference to it."""
 
     def __init__(self, graph: DeviceGraph, cfg: CPRAConfig, lam=None, device="cuda",
-                 z_offset: Optional[torch.Tensor] = None):
+                 z_offset: Optional[torch.Tensor] = None,
+                 node_weight: Optional[np.ndarray] = None):
         if cfg.problem not in ("mis", "maxcut"):
             raise ValueError("problem must be 'mis' or 'maxcut'")
         self.graph = graph
@@ -69,7 +71,7 @@ class CPRASolver:
         self.z_offset = z_offset
         self.model_cfg = api.make_model_cfg(api.SAGE if cfg.layer_kind == "sage" else api.GCN,
                                             cfg.n_layers, in_dim, cfg.hidden, S, cfg.recompute,
-                                            z_offset)
+                                            z_offset, cfg.train_from_layer)
         if cfg.problem == "mis":
             if lam is None:
                 raise ValueError("MIS needs a penalty grid lambda [S]")
@@ -80,8 +82,15 @@ class CPRASolver:
         else:
             self.lam = None
         self.step_counter = torch.zeros(1, dtype=torch.int32, device=device)  # steps done
+        self.node_weight = None  # weighted MIS: float32 [N] or [N, S]
+        if node_weight is not None:
+            nw = np.ascontiguousarray(node_weight, dtype=np.float32)
+            if nw.shape not in ((N,), (N, S)):
+                raise ValueError(f"node weights must be [{N}] or [{N}, {S}]")
+            self.node_weight = torch.from_numpy(nw).to(device)
         self.loss_cfg = api.make_loss_cfg(self.problem_id, S, self.lam, cfg.alpha, 0.0, cfg.nu,
-                                          cfg.std_ddof, None, cfg.gamma_start, cfg.gamma_end, cfg.T)
+                                          cfg.std_ddof, None, cfg.gamma_start, cfg.gamma_end, cfg.T,
+                                          self.node_weight)
         self.adam_cfg = api.AdamCfg(cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay)
         self.step_cfg = api.StepCfg(self.model_cfg, self.loss_cfg, self.adam_cfg)
         self.n_params = api.model_param_count(self.model_cfg, N)
@@ -99,6 +108,15 @@ class CPRASolver:
         self.t = 0
         self._graph = None
         self._stream = None
+
+    def set_reuse_frozen_prefix(self, on: bool) -> None:
+        """Start later forwards at the first trained layer from the activations the
+        previous forward saved (valid with a frozen encoder, after one full forward)."""
+        if on and self.cfg.train_from_layer < 1:
+            raise ValueError("reusing the frozen prefix needs train_from_layer >= 1")
+        self.model_cfg.reuse_frozen_prefix = int(on)
+        self.step_cfg.model.reuse_frozen_prefix = int(on)
+        self.close()  # a captured step would keep the old choice
 
     # -- parameters ---------------------------------------------------------
     def load_params(self, p: Dict[str, object]) -> None:
@@ -222,8 +240,10 @@ class CPRASolver:
         value = torch.empty(G * S, dtype=torch.int64, device=dev)
         viol = torch.empty(G * S, dtype=torch.int64, device=dev)
         ph = torch.empty(G, dtype=torch.int64, device=dev)
-        wv = torch.empty(G * S, dtype=torch.float64, device=dev) if self.graph.weight is not None else None
-        api.round_eval(self.graph, self.problem_id, Z, X, value, viol, wv, ph)
+        weighted = self.graph.weight is not None or self.node_weight is not None
+        wv = torch.empty(G * S, dtype=torch.float64, device=dev) if weighted else None
+        api.round_eval(self.graph, self.problem_id, Z, X, value, viol, wv, ph,
+                       node_weight=self.node_weight)
         torch.cuda.synchronize()
         out = {"X": X[: self.graph.n].cpu().numpy(), "value": value.cpu().numpy().reshape(G, S),
                "violations": viol.cpu().numpy().reshape(G, S), "pair_hamming": ph.cpu().numpy()}

@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = _lib.lib()
-    assert lib.cpra_abi_version() == 2
+    assert lib.cpra_abi_version() == 4
     for code, name in _lib.STATUS.items():
         assert lib.cpra_status_string(code).decode() == name
 

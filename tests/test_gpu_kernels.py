@@ -328,6 +328,7 @@ def test_round_eval_bit_exact(gname, S, problem):
         if problem == "mis":
             assert np.array_equal(val[gi * S:(gi + 1) * S], e["size"])
             assert np.array_equal(vio[gi * S:(gi + 1) * S], e["violations"])
+            assert np.array_equal(wv[gi * S:(gi + 1) * S], e["weight"])  # unit weights: the size
         else:
             assert np.array_equal(val[gi * S:(gi + 1) * S], e["cut_edges"])
             np.testing.assert_allclose(wv[gi * S:(gi + 1) * S], e["cut"], rtol=1e-12)
@@ -364,3 +365,50 @@ def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
                                        f"cfg {cfg} {key} splits {splits}")
     finally:
         a.autotune_reset()
+
+
+# ---------------------------------------------------------------------------
+# Weighted MIS: node weights per node ([N], ld 0) or per head ([N, S])
+@pytest.mark.parametrize("per_head", [False, True])
+@pytest.mark.parametrize("gname,S", [("rrg3_100", 10), ("batch", 7), ("rrg20_500", 130)])
+def test_weighted_mis_loss_and_eval(gname, S, per_head):
+    a = api()
+    g = GRAPHS[gname]()
+    say(f"weighted MIS {gname} S={S} per_head={per_head}")
+    dg = a.DeviceGraph.from_csr(g)
+    rng = np.random.default_rng(S)
+    W = rng.uniform(0, 1, (g.n, S) if per_head else g.n).astype(np.float32)
+    Wd = to_dev(W)
+    Z = random_logits(g.n, S, seed=S + 5)
+    lam = np.logspace(-1, 1, S).astype(np.float32)
+    lam_d = to_dev(lam)
+    gamma, nu = -0.4, 0.1
+    cfg = a.make_loss_cfg(a.MIS, S, lam_d, 2, gamma, nu, 0, node_weight=Wd)
+    ws = torch.empty(a.loss_workspace_bytes(dg, cfg), dtype=torch.uint8, device="cuda")
+    Zd = to_dev(Z)
+    dZ = torch.empty_like(Zd)
+    terms = torch.empty((dg.n_graphs, S + 2), dtype=torch.float64, device="cuda")
+    a.loss_fwd_bwd(dg, cfg, Zd, dZ, terms, ws)
+    G = dg.n_graphs
+    val = torch.empty(G * S, dtype=torch.int64, device="cuda")
+    vio = torch.empty(G * S, dtype=torch.int64, device="cuda")
+    wv = torch.empty(G * S, dtype=torch.float64, device="cuda")
+    a.round_eval(dg, a.MIS, Zd, None, val, vio, wv, node_weight=Wd)
+    torch.cuda.synchronize()
+    T, dZh, wv = terms.cpu().numpy(), dZ.cpu().numpy(), wv.cpu().numpy()
+    Z64, W64 = Z.astype(np.float64), W.astype(np.float64)
+    gp = g.graph_ptr
+    Xo = oev.round_solutions(Z64)
+    for gi in range(len(gp) - 1):
+        lo, hi = int(gp[gi]), int(gp[gi + 1])
+        sub = oobj._slice_graph(g, lo, hi) if len(gp) > 2 else g
+        ref = oobj.loss_terms(Z64[lo:hi], sub, "mis", lam.astype(np.float64), gamma, 2, nu, 0,
+                              W64[lo:hi])
+        for s in range(S):
+            scale = abs(ref["head"][s]) + np.sum(np.abs(oobj.sigmoid_pair(Z64[lo:hi, s])[0])) + 1.0
+            assert_close_scalar(T[gi, s], ref["head"][s], scale, what=f"weighted l_{s}")
+        gref = oobj.grad_wrt_Z(Z64[lo:hi], sub, "mis", lam.astype(np.float64), gamma, 2, nu, 0,
+                               W64[lo:hi])
+        assert_close_array(dZh[lo:hi], gref, what=f"weighted dZ graph {gi}")
+        ev = oev.evaluate_one(Xo[lo:hi], sub, "mis", W64[lo:hi])
+        np.testing.assert_allclose(wv[gi * S:(gi + 1) * S], ev["weight"], rtol=1e-12, atol=1e-12)
