@@ -306,6 +306,20 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
                             void* ws, size_t ws_bytes, cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Solution diversity (Sec. 4.1 Evaluation Metrics; the Hamming-distance and
+ * unique-solution analyses of the diversity appendix): for the S rounded
+ * solutions X (uint8 {0,1} [N, S], ldx >= S; e.g. from cpra_round_eval),
+ *   D[s * ldd + l] = d_H(x_s, x_l)        (int32 [S, S], ldd >= S) or NULL,
+ *   hist[d] = #{s < l : d_H(x_s, x_l) = d} (int64 [N + 1]) or NULL,
+ *   *n_unique = number of distinct solutions among the heads (int32) or NULL.
+ * DScore = 2 / (N S (S-1)) * sum_d d hist[d].  Exact integers; S <= 1024.
+ * ---------------------------------------------------------------------- */
+size_t cpra_pairwise_hamming_workspace_bytes(int32_t N, int32_t S);
+cpra_status cpra_pairwise_hamming(int32_t N, int32_t S, const uint8_t* X, int64_t ldx, int32_t* D,
+                                  int64_t ldd, int64_t* hist, int32_t* n_unique, void* ws,
+                                  size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Learned warm start.  The background section's paragraph on learning
  * generalized heuristics from data describes networks trained over many
  * instances that propose a starting point (a meta-learned initialisation) for

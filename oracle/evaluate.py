@@ -35,6 +35,25 @@ def pairwise_hamming_sum(X: np.ndarray) -> int:
     return int(np.triu(D, k=1).sum())
 
 
+def pairwise_hamming_matrix(X: np.ndarray) -> np.ndarray:
+    """D[s, l] = d_H(X[:, s], X[:, l]) for every pair of heads (int64 [S, S])."""
+    Xi = X.astype(np.int64)
+    ones = Xi.sum(axis=0)
+    return ones[:, None] + ones[None, :] - 2 * (Xi.T @ Xi)
+
+
+def diversity_stats(X: np.ndarray):
+    """Solution-diversity analytics of Sec. 4.1 / the diversity appendix figures:
+    the distance matrix, the histogram of d_H over the S(S-1)/2 pairs (bins 0..N),
+    and the number of distinct solutions among the heads."""
+    N, S = X.shape
+    D = pairwise_hamming_matrix(X)
+    iu = np.triu_indices(S, k=1)
+    hist = np.bincount(D[iu], minlength=N + 1).astype(np.int64)
+    unique = int(np.unique(X.T.astype(np.uint8), axis=0).shape[0]) if S else 0
+    return {"D": D, "hist": hist, "unique": unique}
+
+
 def dscore(X: np.ndarray) -> float:
     N, S = X.shape
     if S < 2 or N == 0:

@@ -96,6 +96,8 @@ PROTOTYPES = {
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),
     "cpra_round_eval_workspace_bytes": (SZ, [PCsr, I32]),
     "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, I64, P, SZ, P]),
+    "cpra_pairwise_hamming_workspace_bytes": (SZ, [I32, I32]),
+    "cpra_pairwise_hamming": (None, [I32, I32, P, I64, P, I64, P, P, P, SZ, P]),
     "cpra_node_features": (None, [PCsr, I32, I32, P, I64, P, I64, P, P]),
     "cpra_mpnn_param_count": (I64, [PMpnn]),
     "cpra_mpnn_param_offsets": (None, [PMpnn, C.POINTER(I64)]),

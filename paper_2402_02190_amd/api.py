@@ -255,6 +255,19 @@ def round_eval(g, problem: int, Z: torch.Tensor, X=None, value=None, violations=
          _ptr(pair_hamming), nw, ld, _ptr(ws), ws.numel(), _stream(stream))
 
 
+def pairwise_hamming(X: torch.Tensor, D: Optional[torch.Tensor] = None,
+                     hist: Optional[torch.Tensor] = None, n_unique: Optional[torch.Tensor] = None,
+                     ws: Optional[torch.Tensor] = None, stream=None):
+    """Pairwise Hamming distances / histogram / distinct count of the columns of
+    a uint8 [N, S] device matrix of rounded solutions."""
+    N, S = X.shape
+    if ws is None:
+        nb = int(_lib.lib().cpra_pairwise_hamming_workspace_bytes(N, S))
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=X.device)
+    call("cpra_pairwise_hamming", N, S, _ptr(X), X.stride(0), _ptr(D), 0 if D is None else D.stride(0),
+         _ptr(hist), _ptr(n_unique), _ptr(ws), ws.numel(), _stream(stream))
+
+
 # ---------------------------------------------------------------- warm start
 def node_features(g, in_dim: int, rand: Optional[torch.Tensor], feat: torch.Tensor,
                   triangles: Optional[torch.Tensor] = None, stream=None):

@@ -226,6 +226,21 @@ class CPRASolver:
             for _ in range(steps):
                 self.step()
 
+    def run_until_binary(self, steps: int, eps: float = 1e-4, check_every: int = 50) -> int:
+        """Replay up to `steps` steps, stopping early once the annealing term per entry,
+        S(P) / (N S), falls below eps (checked every `check_every` steps: the
+        stopping rule of the training-setting appendix and the two-stage appendix).
+        Returns the number of steps run."""
+        done = 0
+        N, S = self.graph.n, self.cfg.S
+        while done < steps:
+            n = min(check_every, steps - done)
+            self.replay(n)
+            done += n
+            if float(self.terms_host()[:, S].sum()) / max(1, N * S) < eps:
+                break
+        return done
+
     def forward(self, stream=None) -> torch.Tensor:
         """Z = GNN(params) without a parameter update."""
         api.model_forward(self.graph, self.model_cfg, self.params, self.Z, self.ws, stream)
@@ -250,6 +265,26 @@ class CPRASolver:
         if wv is not None:
             out["wvalue"] = wv.cpu().numpy().reshape(G, S)
         return out
+
+    def diversity(self, X: Optional[torch.Tensor] = None, graph_index: int = 0) -> Dict[str, object]:
+        """Pairwise Hamming distances, their histogram, the distinct-solution count and
+        DScore of the rounded solutions of one graph (all of them for a single graph)."""
+        if X is None:
+            X = torch.empty((max(self.graph.n, 1), self.cfg.S), dtype=torch.uint8, device=self.device)
+            api.round_eval(self.graph, self.problem_id, self.Z, X)
+        if self.graph.n_graphs > 1:
+            gp = self.graph.graph_ptr.cpu().numpy()
+            X = X[int(gp[graph_index]):int(gp[graph_index + 1])]
+        N, S = X.shape
+        D = torch.empty((S, S), dtype=torch.int32, device=self.device)
+        hist = torch.empty(N + 1, dtype=torch.int64, device=self.device)
+        nu = torch.empty(1, dtype=torch.int32, device=self.device)
+        api.pairwise_hamming(X.contiguous(), D, hist, nu)
+        torch.cuda.synchronize()
+        h = hist.cpu().numpy()
+        total = int(h.dot(np.arange(N + 1)))
+        return {"D": D.cpu().numpy(), "hist": h, "unique": int(nu.item()),
+                "dscore": 2.0 * total / (N * S * (S - 1)) if S > 1 and N else 0.0}
 
     def terms_host(self) -> np.ndarray:
         torch.cuda.synchronize()

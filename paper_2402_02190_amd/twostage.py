@@ -38,19 +38,10 @@ def log(*a):
 
 
 def _run(sol: CPRASolver, T: int, eps: float, K: int = 50):
-    """Replay steps in chunks of K until T steps or the annealing term per entry
-    drops below eps; returns (steps, seconds)."""
-    N, S = sol.graph.n, sol.cfg.S
+    """Steps until T or the stopping rule; returns (steps, seconds)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    while done < T:
-        n = min(K, T - done)
-        sol.replay(n)
-        done += n
-        ent = float(sol.terms_host()[:, S].sum())  # synchronises
-        if ent / (N * S) < eps:
-            break
+    done = sol.run_until_binary(T, eps, K)
     torch.cuda.synchronize()
     return done, time.perf_counter() - t0
 

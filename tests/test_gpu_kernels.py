@@ -412,3 +412,28 @@ def test_weighted_mis_loss_and_eval(gname, S, per_head):
         assert_close_array(dZh[lo:hi], gref, what=f"weighted dZ graph {gi}")
         ev = oev.evaluate_one(Xo[lo:hi], sub, "mis", W64[lo:hi])
         np.testing.assert_allclose(wv[gi * S:(gi + 1) * S], ev["weight"], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,S", [(1, 1), (63, 5), (64, 33), (1000, 100), (3000, 500), (0, 4)])
+def test_pairwise_hamming_bit_exact(N, S):
+    a = api()
+    rng = np.random.default_rng(N + S)
+    X = (rng.random((N, S)) < 0.3).astype(np.uint8)
+    if S > 3 and N > 0:
+        X[:, 3] = X[:, 1]  # a duplicated solution
+    Xd = torch.from_numpy(X).cuda() if N else torch.zeros((0, S), dtype=torch.uint8, device="cuda")
+    D = torch.empty((S, S), dtype=torch.int32, device="cuda")
+    hist = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+    nu = torch.empty(1, dtype=torch.int32, device="cuda")
+    a.pairwise_hamming(Xd, D, hist, nu)
+    torch.cuda.synchronize()
+    ref = oev.diversity_stats(X)
+    assert np.array_equal(D.cpu().numpy(), ref["D"])
+    assert np.array_equal(hist.cpu().numpy(), ref["hist"])
+    assert int(nu.item()) == ref["unique"]
+    # without the matrix: histogram and count alone (the workspace holds D)
+    hist2 = torch.empty_like(hist)
+    nu2 = torch.empty_like(nu)
+    a.pairwise_hamming(Xd, None, hist2, nu2)
+    torch.cuda.synchronize()
+    assert torch.equal(hist2, hist) and torch.equal(nu2, nu)

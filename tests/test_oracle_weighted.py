@@ -91,3 +91,22 @@ def test_evaluate_reports_set_weight():
     ev = evaluate.evaluate_one(X, g, "mis", W)
     for s in range(3):
         assert ev["weight"][s] == pytest.approx(sum(W[i, s] for i in range(g.n) if X[i, s]))
+
+
+# ---------------------------------------------------------------------------
+# Solution-diversity analytics (pairwise Hamming matrix, histogram, unique count)
+def test_diversity_stats_against_brute_force_and_proposition_3_2():
+    rng = np.random.default_rng(4)
+    N, S = 37, 9
+    X = (rng.random((N, S)) < 0.4).astype(np.uint8)
+    X[:, 5] = X[:, 2]  # two duplicated solutions
+    X[:, 7] = X[:, 2]
+    st = evaluate.diversity_stats(X)
+    for s in range(S):
+        for l in range(S):
+            assert st["D"][s, l] == int(np.sum(X[:, s] != X[:, l]))
+    assert st["unique"] == S - 2
+    # total over pairs = sum_i k_i (S - k_i) (Proposition 3.2's counting identity)
+    k = X.astype(np.int64).sum(axis=1)
+    assert st["hist"].dot(np.arange(N + 1)) == int(np.sum(k * (S - k)))
+    assert st["hist"].sum() == S * (S - 1) // 2 and st["hist"][0] == 3  # pairs among {2, 5, 7}
