@@ -258,8 +258,8 @@ def main():
     if args.tuning_file is None and not args.no_autotune:
         args.tuning_file = default_tuning_file(args.workload)
     if args.gpus != 1:
-        log("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its "
-            "own share of graphs; see the sharding note in DESIGN.md). Run with --gpus 1.")
+        log("bench.py measures one GPU: the library runs one process on one GPU (a batch of graphs "
+            "would shard at graph boundaries, one share per GPU). Run with --gpus 1.")
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
