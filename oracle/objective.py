@@ -219,6 +219,7 @@ def batched_loss_terms(Z: np.ndarray, graph, problem, lam, gamma, alpha, nu=0.0,
 class _Sub:
     def __init__(self, row_ptr, col_idx, weight):
         self.row_ptr, self.col_idx, self.weight = row_ptr, col_idx, weight
+        self.graph_ptr = np.array([0, row_ptr.size - 1], dtype=np.int64)  # one graph
 
 
 def _slice_graph(graph, lo: int, hi: int):

@@ -15,7 +15,7 @@ additive form gamma(0) + rate * t.
 
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -95,6 +95,54 @@ def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=
     grads = gnn.backward(params, M, cache, dZ, relu_active)
     if return_cache:
         return Z, terms, dZ, grads, cache
+    return Z, terms, dZ, grads
+
+
+def graph_params(params, b: int, lo: int, hi: int):
+    """The network of graph b of a batch with per-graph weights: rows lo..hi-1 of
+    the embedding and entry b (leading index) of every layer's Ws, Wn and b."""
+    return {"emb": params["emb"][lo:hi],
+            "layers": [{k: v[b] for k, v in L.items()} for L in params["layers"]]}
+
+
+def loss_and_grads_per_graph(params, graph, cfg: StepConfig, gamma: float, relu_active=None,
+                             z_offset=None):
+    """Forward, loss terms and gradients of a block-diagonal batch in which every
+    graph has its own network (layer weights with a leading graph index).
+
+    Each graph is then an independent CPRA problem (Sec. 3.1 applied per
+    instance; the multi-instance use of the heads in Sec. 3.1's last paragraph
+    and the DBM experiment, here with one network per instance): it is cut out
+    of the batch and handed to ``loss_and_grads`` alone, with its rows of the
+    embedding, node weights, z_offset and ReLU decisions, and its results are
+    put back in place.  Returns (Z, terms per graph, dZ, grads) in the batch's
+    layout, the layer gradients with the same leading graph index."""
+    gp = np.asarray(graph.graph_ptr, dtype=np.int64)
+    emb = params["emb"]
+    S = params["layers"][-1]["Ws"].shape[1]
+    N = emb.shape[0]
+    Z = np.zeros((N, S))
+    dZ = np.zeros((N, S))
+    grads = {"emb": np.zeros_like(emb),
+             "layers": [{k: np.zeros_like(v) for k, v in L.items()} for L in params["layers"]]}
+    terms = []
+    nw = None if cfg.node_weight is None else np.asarray(cfg.node_weight)
+    for b in range(gp.size - 1):
+        lo, hi = int(gp[b]), int(gp[b + 1])
+        sub = objective._slice_graph(graph, lo, hi)
+        M = gnn.mean_aggregation_matrix(sub.row_ptr, sub.col_idx)
+        cfg_b = replace(cfg, node_weight=None if nw is None else nw[lo:hi])
+        ra = None if relu_active is None else [m[lo:hi] for m in relu_active]
+        zo = None if z_offset is None else np.asarray(z_offset)[lo:hi]
+        Zb, tb, dZb, gb = loss_and_grads(graph_params(params, b, lo, hi), M, sub, cfg_b, gamma,
+                                         ra, z_offset=zo)
+        Z[lo:hi] = Zb
+        dZ[lo:hi] = dZb
+        terms.extend(tb)
+        grads["emb"][lo:hi] = gb["emb"]
+        for Lg, Lb in zip(grads["layers"], gb["layers"]):
+            for k in Lg:
+                Lg[k][b] = Lb[k]
     return Z, terms, dZ, grads
 
 

@@ -17,5 +17,6 @@ from .graphs import (  # noqa: F401
     induced_subgraph,
     bfs_ball,
 )
-from .params import init_mpnn_params, init_params, param_shapes, random_channels  # noqa: F401
+from .params import init_mpnn_params, init_params, init_params_per_graph, param_shapes, \
+    random_channels  # noqa: F401
 from .presets import PRESETS, Preset, get_preset  # noqa: F401

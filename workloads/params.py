@@ -69,6 +69,32 @@ def init_params(kind: str, n_nodes: int, n_layers: int, hidden: int, S: int,
     return {"emb": emb, "layers": layers}
 
 
+def init_params_per_graph(kind: str, n_nodes: int, n_layers: int, hidden: int, S: int,
+                          n_graphs: int, seed: int, in_dim: int = None) -> Dict[str, object]:
+    """Seeded float32 parameters with one network per graph of a batch: the
+    embedding as in init_params, and every layer's Ws, Wn [G, out_k, in_k] and
+    b [G, out_k] with the same per-entry distributions, graph g's matrices drawn
+    after graph g-1's."""
+    if kind not in LAYER_KINDS:
+        raise ValueError(f"layer kind must be one of {LAYER_KINDS}")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = param_shapes(kind, n_nodes, n_layers, hidden, S, in_dim)
+    emb = rng.standard_normal(shapes["emb"], dtype=np.float32)
+    layers: List[Dict[str, np.ndarray]] = []
+    for sh in shapes["layers"]:
+        d_out, d_in = sh["Ws"]
+        bound = 1.0 / np.sqrt(d_in)
+        layer = {"Ws": np.empty((n_graphs, d_out, d_in), np.float32),
+                 "Wn": np.empty((n_graphs, d_out, d_in), np.float32)}
+        for g in range(n_graphs):
+            layer["Ws"][g] = rng.uniform(-bound, bound, size=(d_out, d_in))
+            layer["Wn"][g] = rng.uniform(-bound, bound, size=(d_out, d_in))
+        if kind == "sage":
+            layer["b"] = np.zeros((n_graphs, d_out), dtype=np.float32)
+        layers.append(layer)
+    return {"emb": emb, "layers": layers}
+
+
 def random_logits(n: int, S: int, seed: int, scale: float = 2.0,
                   near_binary: bool = False) -> np.ndarray:
     """Logit matrices for kernel-level tests and benchmarks.
