@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 4
+#define CPRA_ABI_VERSION 5
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -129,6 +129,34 @@ cpra_status cpra_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, in
                       void* ws, size_t ws_bytes, cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Grouped FP32 GEMM over the graphs of a block-diagonal batch in which every
+ * graph has its own weights (Sec. 3.1's multi-instance use of the heads, with
+ * one network per instance).  Graph g owns rows graph_ptr[g] .. graph_ptr[g+1]-1
+ * of g->graph_ptr (a single graph when g->n_graphs <= 1: the plain product).
+ *  mode CPRA_GROUP_ROWS (M = n_nodes):
+ *    C[rows of g, :N] = act( A[rows of g, :K] op(B_g) + bias_g ),
+ *    B_g = B + g * b_stride: [N,K] (ldb >= K) if trans_b, else [K,N] (ldb >= N);
+ *    bias_g = bias + g * bias_stride ([N], may be NULL); act = ReLU if relu;
+ *    A [n_nodes, K] (lda >= K), C [n_nodes, N] (ldc >= N).
+ *  mode CPRA_GROUP_K (K = n_nodes; trans_b = 0, no bias, no relu):
+ *    C_g[:M, :N] = A[rows of g, :M]^T B[rows of g, :N] at C + g * c_stride (ldc >= N),
+ *    and, when bias_grad is not NULL, bias_grad[g * bg_stride + m] = sum over
+ *    the rows of g of A[r, m] (the bias gradient of graph g's layer);
+ *    A [n_nodes, M] (lda >= M), B [n_nodes, N] (ldb >= N).
+ * Per-graph blocks must not overlap (strides at least one block's span).
+ * Workspace: cpra_gemm_grouped_workspace_bytes (rows: the row-tile maps, built
+ * on every call; K: split-K partials, may be 0).  Borrowed, caller-owned. */
+enum { CPRA_GROUP_ROWS = 1, CPRA_GROUP_K = 2 };
+size_t cpra_gemm_grouped_workspace_bytes(const cpra_csr* g, int32_t mode, int32_t M, int32_t N,
+                                         int32_t with_bias_grad);
+cpra_status cpra_gemm_grouped(const cpra_csr* g, int32_t mode, int32_t trans_b, int32_t M,
+                              int32_t N, int32_t K, const float* A, int64_t lda, const float* B,
+                              int64_t ldb, int64_t b_stride, float* C, int64_t ldc,
+                              int64_t c_stride, const float* bias, int64_t bias_stride,
+                              float* bias_grad, int64_t bg_stride, int32_t relu, void* ws,
+                              size_t ws_bytes, cpra_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Relaxed CPRA objective and its gradient (Sec. 3.1 Eq. CPRA-loss-function-GNN,
  * Sec. 3.2 penalty-diversified form, Sec. 3.3 Eq. CPRA-loss-function-GNN-variation,
  * objective table of the problem-specification appendix):
@@ -189,6 +217,10 @@ cpra_status cpra_sigmoid(int32_t N, int32_t S, const float* Z, int64_t ldz, floa
  * Flat parameter layout (float32), offsets from cpra_model_param_offsets:
  *   [embedding N*in_dim] then per layer k: Ws [out_k*in_k], Wn [out_k*in_k],
  *   b [out_k] (SAGE only; absent for GCN).  Each matrix row-major [out, in].
+ * With weight_groups = G > 1 (one network per graph of a batch of G graphs)
+ *   every layer block holds G copies back to back: Ws [G][out_k][in_k], then
+ *   Wn [G][out_k][in_k], then b [G][out_k]; graph g's rows of the batch use
+ *   copy g (the embedding is per node already).
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t layer_kind; /* CPRA_GCN (no bias) or CPRA_SAGE (one bias per layer) */
@@ -215,6 +247,11 @@ typedef struct {
    * neighbour aggregate is reused too).  The caller guarantees that such a
    * forward ran on this workspace with the same frozen parameters. */
   int32_t reuse_frozen_prefix;
+  /* 0 or 1: one set of layer weights shared by all graphs of a batch.
+   * G > 1: one set per graph (the batch's graphs are then independent CPRA
+   * problems trained in the same launches); G must equal the graph's
+   * n_graphs at every call. */
+  int32_t weight_groups;
 } cpra_model_cfg;
 
 /* Total float count including the embedding; -1 on invalid config. */

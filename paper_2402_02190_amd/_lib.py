@@ -44,7 +44,7 @@ class ModelCfg(C.Structure):
     _fields_ = [("layer_kind", C.c_int32), ("n_layers", C.c_int32), ("in_dim", C.c_int32),
                 ("hidden", C.c_int32), ("S", C.c_int32), ("recompute", C.c_int32),
                 ("z_offset", C.c_void_p), ("train_from_layer", C.c_int32),
-                ("reuse_frozen_prefix", C.c_int32)]
+                ("reuse_frozen_prefix", C.c_int32), ("weight_groups", C.c_int32)]
 
 
 class AdamCfg(C.Structure):
@@ -81,6 +81,9 @@ PROTOTYPES = {
     "cpra_aggregate_mean": (None, [PCsr, I32, I32, P, I64, P, I64, P, I64, P, I32, P, I64, P]),
     "cpra_gemm_workspace_bytes": (SZ, [I32, I32, I32, I32, I32]),
     "cpra_gemm": (None, [I32, I32, I32, I32, I32, P, I64, P, I64, F32, P, I64, P, I32, P, SZ, P]),
+    "cpra_gemm_grouped_workspace_bytes": (SZ, [PCsr, I32, I32, I32, I32]),
+    "cpra_gemm_grouped": (None, [PCsr, I32, I32, I32, I32, I32, P, I64, P, I64, I64, P, I64, I64,
+                                 P, I64, P, I64, I32, P, SZ, P]),
     "cpra_loss_workspace_bytes": (SZ, [PCsr, PLoss]),
     "cpra_loss_fwd_bwd": (None, [PCsr, PLoss, P, I64, P, I64, P, I64, P, P, SZ, P]),
     "cpra_sigmoid": (None, [I32, I32, P, I64, P, I64, P]),

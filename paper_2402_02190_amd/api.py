@@ -126,6 +126,47 @@ def gemm(A: torch.Tensor, B: torch.Tensor, C_out: torch.Tensor, trans_a=False, t
     return C_out
 
 
+GROUP_ROWS, GROUP_K = 1, 2
+
+
+def gemm_grouped_workspace_bytes(g, mode: int, M: int, N: int, with_bias_grad=False) -> int:
+    return int(_lib.lib().cpra_gemm_grouped_workspace_bytes(_csr(g), int(mode), M, N,
+                                                            int(with_bias_grad)))
+
+
+def gemm_grouped_rows(g, A: torch.Tensor, B: torch.Tensor, C_out: torch.Tensor, trans_b=False,
+                      bias: Optional[torch.Tensor] = None, relu=False, ws=None, stream=None):
+    """Per graph g of the batch: C[rows of g] = act(A[rows of g] op(B[g]) + bias[g]).
+    B [G, N, K] (trans_b) or [G, K, N]; bias [G, N] or None; A [n, K]; C [n, N]."""
+    M, K = A.shape
+    N = B.shape[1] if trans_b else B.shape[2]
+    if ws is None:
+        nb = gemm_grouped_workspace_bytes(g, GROUP_ROWS, M, N)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=C_out.device)
+    call("cpra_gemm_grouped", _csr(g), GROUP_ROWS, int(trans_b), M, N, K, _ptr(A), A.stride(0),
+         _ptr(B), B.stride(1), B.stride(0), _ptr(C_out), C_out.stride(0), 0, _ptr(bias),
+         0 if bias is None else bias.stride(0), None, 0, int(relu), _ptr(ws), ws.numel(),
+         _stream(stream))
+    return C_out
+
+
+def gemm_grouped_k(g, A: torch.Tensor, B: torch.Tensor, C_out: torch.Tensor,
+                   bias_grad: Optional[torch.Tensor] = None, ws=None, stream=None):
+    """Per graph g of the batch: C[g] = A[rows of g]^T B[rows of g] and optionally
+    bias_grad[g] = the column sums of A over the rows of g.  A [n, M], B [n, N],
+    C [G, M, N], bias_grad [G, M]."""
+    K, M = A.shape
+    N = B.shape[1]
+    if ws is None:
+        nb = gemm_grouped_workspace_bytes(g, GROUP_K, M, N, bias_grad is not None)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=C_out.device) if nb else None
+    call("cpra_gemm_grouped", _csr(g), GROUP_K, 0, M, N, K, _ptr(A), A.stride(0), _ptr(B),
+         B.stride(0), 0, _ptr(C_out), C_out.stride(1), C_out.stride(0), None, 0, _ptr(bias_grad),
+         0 if bias_grad is None else bias_grad.stride(0), 0, _ptr(ws),
+         0 if ws is None else ws.numel(), _stream(stream))
+    return C_out
+
+
 def _node_weight_args(node_weight: Optional[torch.Tensor]):
     """(pointer, leading dimension) of MIS node weights: [N] (ld 0) or [N, S]."""
     if node_weight is None:
@@ -168,17 +209,19 @@ def sigmoid(Z: torch.Tensor, P: torch.Tensor, stream=None):
 
 def make_model_cfg(layer_kind: int, n_layers: int, in_dim: int, hidden: int, S: int,
                    recompute: bool = False, z_offset: torch.Tensor = None,
-                   train_from_layer: int = 0, reuse_frozen_prefix: bool = False) -> ModelCfg:
+                   train_from_layer: int = 0, reuse_frozen_prefix: bool = False,
+                   weight_groups: int = 0) -> ModelCfg:
     """z_offset: optional float32 [N, S] contiguous device tensor of fixed logits added to
     the output (the warm start); the caller keeps it alive while the config is used.
-    train_from_layer / reuse_frozen_prefix: a frozen encoder (see include/cpra.h)."""
+    train_from_layer / reuse_frozen_prefix: a frozen encoder (see include/cpra.h).
+    weight_groups: G > 1 gives every graph of a G-graph batch its own layer weights."""
     if z_offset is not None:
         if z_offset.dtype != torch.float32 or not z_offset.is_contiguous() or z_offset.dim() != 2 \
                 or z_offset.shape[1] != S:
             raise ValueError("z_offset must be a contiguous float32 [N, S] tensor")
     return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute),
                     None if z_offset is None else z_offset.data_ptr(), int(train_from_layer),
-                    int(reuse_frozen_prefix))
+                    int(reuse_frozen_prefix), int(weight_groups))
 
 
 def model_param_count(cfg: ModelCfg, n_nodes: int) -> int:

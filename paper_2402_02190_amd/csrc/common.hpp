@@ -109,6 +109,18 @@ struct GemmPiece {
   int K;
 };
 
+// Row tiles of a block-diagonal batch that never cross a graph boundary, for
+// each row-tile height BM = 32, 64, 128: {graph, first row, end row, 0} per
+// tile, graph -1 past the last tile.  Built on the device by group_rows_build.
+struct GroupRows {
+  const int4* map[3];
+  int count[3];
+};
+size_t group_rows_bytes(const cpra_csr* g);
+cpra_status group_rows_build(const cpra_csr* g, void* ws, GroupRows* out, hipStream_t stream);
+// The maps that group_rows_build wrote into ws earlier (no launch).
+cpra_status group_rows_view(const cpra_csr* g, void* ws, GroupRows* out);
+
 struct GemmProblem {
   GemmPiece piece[2];  // the contraction runs over piece[0].K then piece[1].K
   int n_pieces;
@@ -125,6 +137,17 @@ struct GemmProblem {
   int64_t ld_sig;
   const float* add;  // [M, N] (ld_add): added to the result after the bias, or null
   int64_t ld_add;
+  // One weight set per graph of a block-diagonal batch (all problems of a
+  // launch alike; n_groups <= 1 is the plain product):
+  //  1 = by rows: rows of A and C split by graph (A [M, K] with M = batch rows),
+  //      graph g's B and bias at g * b_stride / g * bias_stride floats;
+  //  2 = by K: C_g = A[rows of g]^T B[rows of g] (A^T B with K = batch rows),
+  //      graph g's C and bias_grad at g * c_stride / g * bg_stride floats.
+  int group_mode;
+  int n_groups;
+  const int32_t* group_ptr;  // [n_groups + 1] graph row offsets (device; mode 2)
+  const GroupRows* rows;     // row tiles (mode 1)
+  int64_t b_stride, c_stride, bias_stride, bg_stride;
 };
 
 // Up to 4 independent problems in one launch, all with the same operand layout.

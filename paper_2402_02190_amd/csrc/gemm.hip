@@ -1,16 +1,7 @@
 // FP32 GEMM on the CDNA matrix cores (v_mfma_f32_32x32x2f32) for the GNN's
 // dense weight products: forward X W^T, input gradient dY W and weight
-// gradient dY^T X.
-//
-// A block computes a BM x BN tile with WM x WN wavefronts, each owning
-// TM x TN = (BM/32/WM) x (BN/32/WN) accumulators of 32 x 32.  K advances in
-// BK-deep steps staged through LDS in the [k][mn] layout (double buffered,
-// one barrier per step): the next step's global loads are issued before the
-// current step's MFMAs, all MFMA operands of a step are read from LDS into
-// registers before the first MFMA of the step, and K-contiguous operands are
-// transposed while being written to LDS so every operand read is 32
-// consecutive floats per half-wavefront.  Interior tiles take unguarded
-// float4 loads (a uniform branch); edge tiles fall back to guarded loads.
+// gradient dY^T X.  The kernel template is in gemm_kernel.hpp; this file
+// holds the plain instantiations, planning, autotuning and the entry points.
 //
 // One launch runs up to four independent problems.
 // A problem's contraction may be split in two K pieces with separate
@@ -31,332 +22,14 @@
 #include <string>
 #include <vector>
 
-#include "common.hpp"
+#include "gemm_kernel.hpp"
 
 namespace cpra {
 
 namespace {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+using namespace gemmk;
 
-constexpr int kMaxProblems = 4;
-
-struct ProbDev {
-  const float* A[2];
-  const float* B[2];
-  int64_t lda[2], ldb[2];
-  int K[2];
-  int vecA[2], vecB[2];
-  int n_pieces;
-  float* C;
-  int64_t ldc;
-  int M, N;
-  const float* bias;
-  const float* mask;
-  int64_t ld_mask;
-  float beta;
-  int relu;
-  float* bias_grad;  // [M] row sums of op(A) over K (computed by the first column tile), or null
-  float* sig_out;    // [M, N] (ld_sig): sigmoid of the result, or null
-  int64_t ld_sig;
-  const float* add;  // [M, N] (ld_add): extra addend, or null
-  int64_t ld_add;
-  int n_eff;         // N + 1 when bias_grad is set
-  int tiles_m, tiles_n;
-  int64_t part_off;  // float offset of this problem's split-K partials
-};
-
-struct LaunchArgs {
-  ProbDev p[kMaxProblems];
-  int n_prob;
-  int splits;
-  int grid_x;  // no split: blocks per problem (a multiple of 8); split-K: tiles per group
-  float* partial;
-};
-
-// One operand tile [BK][R] in LDS, loaded by NT threads as float4 vectors.
-template <int R, int BK, int NT, bool KCONTIG>
-struct Tile {
-  static constexpr int PAD = KCONTIG ? 1 : 4;
-  static constexpr int LD = R + PAD;  // LDS row stride (floats)
-  static constexpr int NV = R * BK / 4 / NT;
-  static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
-  float4 reg[NV];
-
-  __device__ inline void load(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim, int k0,
-                              int k_lim, bool vec_ok, int tid) {
-    const bool full = vec_ok && (mn0 + R <= mn_lim) && (k0 + BK <= k_lim);
-    if (full) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int idx = tid + v * NT;
-        if constexpr (KCONTIG) {
-          const int r = idx / (BK / 4);
-          const int kq = (idx % (BK / 4)) * 4;
-          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(mn0 + r) * ld + k0 + kq);
-        } else {
-          const int k = idx / (R / 4);
-          const int rq = (idx % (R / 4)) * 4;
-          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(k0 + k) * ld + mn0 + rq);
-        }
-      }
-      return;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * NT;
-      if constexpr (KCONTIG) {
-        const int r = idx / (BK / 4);
-        const int kq = (idx % (BK / 4)) * 4;
-        const int gm = mn0 + r, gk = k0 + kq;
-        const bool rok = gm < mn_lim;
-        const float* p = X + (int64_t)(rok ? gm : 0) * ld;
-        reg[v].x = (rok && gk + 0 < k_lim) ? p[gk + 0] : 0.f;
-        reg[v].y = (rok && gk + 1 < k_lim) ? p[gk + 1] : 0.f;
-        reg[v].z = (rok && gk + 2 < k_lim) ? p[gk + 2] : 0.f;
-        reg[v].w = (rok && gk + 3 < k_lim) ? p[gk + 3] : 0.f;
-      } else {
-        const int k = idx / (R / 4);
-        const int rq = (idx % (R / 4)) * 4;
-        const int gk = k0 + k, gm = mn0 + rq;
-        const bool kok = gk < k_lim;
-        const float* p = X + (int64_t)(kok ? gk : 0) * ld;
-        reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : 0.f;
-        reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : 0.f;
-        reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : 0.f;
-        reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : 0.f;
-      }
-    }
-  }
-
-  __device__ inline void store(float* __restrict__ Xs, int tid) const {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int idx = tid + v * NT;
-      if constexpr (KCONTIG) {
-        const int r = idx / (BK / 4);
-        const int kq = (idx % (BK / 4)) * 4;
-        Xs[(kq + 0) * LD + r] = reg[v].x;
-        Xs[(kq + 1) * LD + r] = reg[v].y;
-        Xs[(kq + 2) * LD + r] = reg[v].z;
-        Xs[(kq + 3) * LD + r] = reg[v].w;
-      } else {
-        const int k = idx / (R / 4);
-        const int rq = (idx % (R / 4)) * 4;
-        *reinterpret_cast<float4*>(Xs + k * LD + rq) = reg[v];
-      }
-    }
-  }
-};
-
-// C[row, col] = mask(relu(v + beta C)) and optionally sigmoid(C) into sig_out.
-__device__ inline void epilogue_store(const ProbDev& P, int row, int col, float v) {
-  float* cp = P.C + (int64_t)row * P.ldc + col;
-  if (P.add) v += P.add[(int64_t)row * P.ld_add + col];
-  if (P.beta != 0.f) v += P.beta * *cp;
-  if (P.relu) v = fmaxf(v, 0.f);
-  if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
-  *cp = v;
-  if (P.sig_out) {
-    const float e = expf(-fabsf(v));
-    const float r = 1.0f / (1.0f + e);
-    P.sig_out[(int64_t)row * P.ld_sig + col] = v >= 0.0f ? r : e * r;
-  }
-}
-
-// A_T: A stored [K, M] (M contiguous); otherwise [M, K].
-// B_T: B stored [N, K] (K contiguous); otherwise [K, N].
-// PF: prefetch distance in K tiles (1: the next tile is loaded while the
-// current one is multiplied; 2: two tiles ahead, in two register sets, so a
-// load has two K steps of MFMA work to land).
-template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
-  constexpr int NT = 64 * WM * WN;
-  constexpr int TM = BM / (32 * WM);  // 32x32 accumulators per wave along M
-  constexpr int TN = BN / (32 * WN);
-  static_assert(TM >= 1 && TN >= 1 && TM * 32 * WM == BM && TN * 32 * WN == BN, "bad tiling");
-  using TA = Tile<BM, BK, NT, !A_T>;
-  using TB = Tile<BN, BK, NT, B_T>;
-  __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
-
-  // XCD-aware order: the hardware deals consecutive block ids round-robin to
-  // the 8 XCDs, each with its own L2.
-  //  * no split (grid = tiles x problems): each XCD gets a contiguous run of
-  //    tiles, so neighbouring N tiles share their A panel in that XCD's L2;
-  //  * split-K (1-D grid): all tiles of one (problem, split) group -- which
-  //    read the same K rows of A and B -- go to the same XCD.
-  int prob, split, tile;
-  if (args.splits == 1) {
-    prob = blockIdx.y;
-    split = 0;
-    const int per_xcd = args.grid_x / 8;
-    tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  } else {
-    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
-    const int group = x + 8 * (j / args.grid_x);  // grid_x = tiles per group here
-    tile = j % args.grid_x;
-    if (group >= args.n_prob * args.splits) return;
-    prob = group / args.splits;
-    split = group % args.splits;
-  }
-  const ProbDev& P = args.p[prob];
-  if (tile >= P.tiles_m * P.tiles_n) return;
-  const int tm_idx = tile / P.tiles_n;
-  const int tn_idx = tile % P.tiles_n;
-  const int m0 = tm_idx * BM;
-  const int n0 = tn_idx * BN;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int half = lane >> 5, l32 = lane & 31;
-
-  const int nt0 = (P.K[0] + BK - 1) / BK;
-  const int nt1 = P.n_pieces > 1 ? (P.K[1] + BK - 1) / BK : 0;
-  const int KT = nt0 + nt1;
-  const int per_split = (KT + args.splits - 1) / args.splits;
-  const int kt_begin = min(KT, split * per_split);
-  const int kt_end = min(KT, kt_begin + per_split);
-
-  floatx16 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  auto load_into = [&](TA& ta, TB& tb, int kt) {
-    const int pc = kt < nt0 ? 0 : 1;
-    const int k0 = (kt - (pc ? nt0 : 0)) * BK;
-    ta.load(P.A[pc], P.lda[pc], m0, P.M, k0, P.K[pc], P.vecA[pc] != 0, tid);
-    tb.load(P.B[pc], P.ldb[pc], n0, P.N, k0, P.K[pc], P.vecB[pc] != 0, tid);
-  };
-  // Bias gradient (row sums of op(A) over this block's K range): the blocks of
-  // the first column tile add up the staged A tile with plain VALU adds, thread
-  // t owning row t % BM and a fixed slice of each tile's BK rows (zero padding
-  // outside the matrix is already in the tile).
-  constexpr int BG = NT / BM > 0 ? NT / BM : 1;  // threads per row
-  static_assert(BK % BG == 0, "bias slice");
-  const bool do_bias = P.bias_grad != nullptr && tn_idx == 0;
-  const int b_row = tid % BM, b_grp = tid / BM;
-  float bsum = 0.f;
-
-  // multiply the tile staged in LDS buffer `cur` (and add its A rows for the bias)
-  auto compute = [&](int cur) {
-    const float* as = As[cur];
-    const float* bs = Bs[cur];
-    if (do_bias && b_grp < BG) {
-#pragma unroll
-      for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
-    }
-    float af[BK / 2][TM], bf[BK / 2][TN];
-#pragma unroll
-    for (int kk = 0; kk < BK / 2; ++kk) {
-      const int kr = 2 * kk + half;
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK / 2; ++kk)
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
-  };
-
-  if constexpr (PF == 1) {
-    TA ta;
-    TB tb;
-    if (kt_begin < kt_end) {
-      load_into(ta, tb, kt_begin);
-      ta.store(As[0], tid);
-      tb.store(Bs[0], tid);
-      __syncthreads();
-      for (int kt = kt_begin; kt < kt_end; ++kt) {
-        const int cur = (kt - kt_begin) & 1;
-        const bool more = kt + 1 < kt_end;
-        if (more) load_into(ta, tb, kt + 1);
-        compute(cur);
-        if (more) {
-          ta.store(As[cur ^ 1], tid);
-          tb.store(Bs[cur ^ 1], tid);
-        }
-        __syncthreads();
-      }
-    }
-  } else {
-    // Two register sets; the loop is unrolled by two so that every set is
-    // named statically.  In the body for tile kt: LDS[cur] holds tile kt, set
-    // `nxt` holds tile kt + 1 (stored to LDS[cur ^ 1] at the end), and set
-    // `fre` (whose tile kt is already in LDS) receives tile kt + 2.
-    TA ta0, ta1;
-    TB tb0, tb1;
-    auto body = [&](int kt, int cur, TA& fre_a, TB& fre_b, TA& nxt_a, TB& nxt_b) {
-      if (kt + 2 < kt_end) load_into(fre_a, fre_b, kt + 2);
-      compute(cur);
-      if (kt + 1 < kt_end) {
-        nxt_a.store(As[cur ^ 1], tid);
-        nxt_b.store(Bs[cur ^ 1], tid);
-      }
-      __syncthreads();
-    };
-    if (kt_begin < kt_end) {
-      load_into(ta0, tb0, kt_begin);
-      ta0.store(As[0], tid);
-      tb0.store(Bs[0], tid);
-      if (kt_begin + 1 < kt_end) load_into(ta1, tb1, kt_begin + 1);
-      __syncthreads();
-      for (int kt = kt_begin; kt < kt_end; kt += 2) {
-        body(kt, 0, ta0, tb0, ta1, tb1);
-        if (kt + 1 < kt_end) body(kt + 1, 1, ta1, tb1, ta0, tb0);
-      }
-    }
-  }
-
-  // Accumulator layout of the 32x32 MFMA: register r of lane l holds
-  // D[8*(r/4) + 4*(l/32) + r%4][l%32].
-  const bool partial = args.splits > 1;
-  float* part = partial ? args.partial + P.part_off + (int64_t)split * P.M * P.n_eff : nullptr;
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + (wn * TN + j) * 32 + l32;
-      if (col >= P.N) continue;
-      const float bv = (!partial && P.bias) ? P.bias[col] : 0.f;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + (wm * TM + i) * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
-        if (row >= P.M) continue;
-        const float v = acc[i][j][r];
-        if (partial) {
-          part[(int64_t)row * P.n_eff + col] = v;
-        } else {
-          epilogue_store(P, row, col, v + bv);
-        }
-      }
-    }
-  }
-  if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
-    float* red = As[0];
-    if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
-    __syncthreads();
-    if (tid < BM && m0 + tid < P.M) {
-      float v = 0.f;
-      for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
-      if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
-      else P.bias_grad[m0 + tid] = v;
-    }
-  }
-}
-
-// Sum split-K partials in split order and apply the epilogue.
 // Sum split-K partials and apply the epilogue.  A block covers 64 consecutive
 // outputs with 4 groups of 64 threads; group g adds the g-th quarter of the
 // splits in split order (loads issued eight at a time so their latencies
@@ -367,7 +40,8 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void k_gemm_splitk_reduce(L
   __shared__ float red[kRedGroups][kRedElems];
   const int prob = blockIdx.y;
   const ProbDev& P = args.p[prob];
-  const int64_t total = (int64_t)P.M * P.n_eff;
+  const int64_t per_g = (int64_t)P.M * P.n_eff;  // one graph's outputs (mode 2), else all
+  const int64_t total = per_g * args.G;
   const int e = threadIdx.x % kRedElems, grp = threadIdx.x / kRedElems;
   const int64_t idx = (int64_t)blockIdx.x * kRedElems + e;
   if ((int64_t)blockIdx.x * kRedElems >= total) return;  // uniform per block
@@ -392,49 +66,21 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void k_gemm_splitk_reduce(L
   v = red[0][e];
 #pragma unroll
   for (int g2 = 1; g2 < kRedGroups; ++g2) v += red[g2][e];
-  const int row = (int)(idx / P.n_eff);
-  const int col = (int)(idx - (int64_t)row * P.n_eff);
+  const int g = (int)(idx / per_g);
+  const int64_t rem = idx - (int64_t)g * per_g;
+  const int row = (int)(rem / P.n_eff);
+  const int col = (int)(rem - (int64_t)row * P.n_eff);
   if (col == P.N) {
-    P.bias_grad[row] = v;
+    P.bias_grad[(int64_t)g * P.bg_stride + row] = v;
     return;
   }
   if (P.bias) v += P.bias[col];
-  epilogue_store(P, row, col, v);
+  epilogue_store(P, P.C + (int64_t)g * P.c_stride, row, col, v);
 }
 
 inline bool vec_ok(const float* p, int64_t ld) {
   return (reinterpret_cast<uintptr_t>(p) % 16 == 0) && (ld % 4 == 0);
 }
-
-// ---- configurations -------------------------------------------------------
-struct Cfg {
-  int bm, bn, bk, wm, wn;
-};
-constexpr Cfg kCfgs[] = {
-    {64, 64, 32, 2, 2},    // 0: 256 threads, one 32x32 accumulator per wave
-    {64, 64, 32, 2, 1},    // 1: 128 threads, 32x64 per wave
-    {64, 64, 32, 1, 1},    // 2: 64 threads, 64x64 per wave
-    {128, 64, 32, 2, 2},   // 3: 256 threads, 64x32 per wave
-    {64, 128, 32, 2, 2},   // 4: 256 threads, 32x64 per wave
-    {128, 128, 32, 2, 2},  // 5: 256 threads, 64x64 per wave
-    {64, 64, 16, 2, 2},    // 6
-    {128, 128, 16, 2, 2},  // 7
-    {32, 64, 32, 1, 1},    // 8: 64 threads, 32x64 per wave
-    {64, 32, 32, 1, 1},    // 9: 64 threads, 64x32 per wave
-    // prefetch distance 2 (tiles loaded two K steps ahead)
-    {64, 64, 16, 2, 2},    // 10
-    {64, 64, 32, 2, 2},    // 11
-    {128, 64, 16, 2, 2},   // 12
-    {64, 128, 16, 2, 2},   // 13
-    {128, 128, 16, 2, 2},  // 14
-    // prefetch distance 2 with more than one accumulator per wave (fewer, busier waves)
-    {64, 32, 16, 1, 1},    // 15: 64 threads, 64x32 per wave
-    {32, 64, 16, 1, 1},    // 16: 64 threads, 32x64 per wave
-    {64, 64, 16, 1, 1},    // 17: 64 threads, 64x64 per wave
-    {64, 64, 16, 2, 1},    // 18: 128 threads, 32x64 per wave
-    {128, 64, 16, 2, 1},   // 19: 128 threads, 64x64 per wave
-};
-constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 const char* kCfgNames[kNumCfgs] = {"64x64x32_w2x2",   "64x64x32_w2x1", "64x64x32_w1x1",
                                    "128x64x32_w2x2",  "64x128x32_w2x2", "128x128x32_w2x2",
@@ -459,15 +105,25 @@ int total_k_tiles(const GemmProblem& q, int bk) {
   return kt;
 }
 
+// graphs of a grouped problem (1 when not grouped)
+inline int groups_of(const GemmProblem& q) { return q.group_mode ? max(1, q.n_groups) : 1; }
+
 int64_t tiles_of(const GemmProblem* probs, int n, const Cfg& c) {
   int64_t t = 0;
-  for (int i = 0; i < n; ++i) t += ceil_div(probs[i].M, c.bm) * ceil_div(tile_cols_of(probs[i]), c.bn);
+  for (int i = 0; i < n; ++i) {
+    const GemmProblem& q = probs[i];
+    const int64_t cols = ceil_div(tile_cols_of(q), c.bn);
+    if (q.group_mode == 1) t += (ceil_div(q.M, c.bm) + groups_of(q)) * cols;  // row tiles (bound)
+    else t += groups_of(q) * ceil_div(q.M, c.bm) * cols;
+  }
   return t;
 }
 
+// K steps of the longest problem (mode 2: of a graph of average size)
 int max_k_tiles(const GemmProblem* probs, int n, int bk) {
   int m = 0;
-  for (int i = 0; i < n; ++i) m = max(m, total_k_tiles(probs[i], bk));
+  for (int i = 0; i < n; ++i)
+    m = max(m, (int)ceil_div(total_k_tiles(probs[i], bk), probs[i].group_mode == 2 ? groups_of(probs[i]) : 1));
   return m;
 }
 
@@ -475,6 +131,7 @@ int max_k_tiles(const GemmProblem* probs, int n, int bk) {
 constexpr int kMaxSplits = 256;
 
 int heuristic_splits(const GemmProblem* probs, int n, const Cfg& c) {
+  if (probs[0].group_mode == 1) return 1;  // row-grouped products are never split
   const int64_t tiles = tiles_of(probs, n, c);
   const int mkt = max_k_tiles(probs, n, c.bk);
   if (tiles >= 512 || mkt < 8) return 1;
@@ -493,7 +150,7 @@ Plan heuristic_plan(const GemmProblem* probs, int n, bool can_split) {
 size_t partial_floats(int splits, const GemmProblem* probs, int n) {
   if (splits <= 1) return 0;
   size_t f = 0;
-  for (int i = 0; i < n; ++i) f += (size_t)splits * probs[i].M * n_eff_of(probs[i]);
+  for (int i = 0; i < n; ++i) f += (size_t)splits * groups_of(probs[i]) * probs[i].M * n_eff_of(probs[i]);
   return f;
 }
 
@@ -513,6 +170,10 @@ std::string shape_key(bool a_t, bool b_t, const GemmProblem* probs, int n) {
   std::string k = a_t ? "T" : "N";
   k += b_t ? "T" : "N";
   char buf[96];
+  if (probs[0].group_mode) {  // per-graph weights: mode and graph count
+    snprintf(buf, sizeof(buf), "|g%d:%d", probs[0].group_mode, groups_of(probs[0]));
+    k += buf;
+  }
   for (int i = 0; i < n; ++i) {
     const GemmProblem& q = probs[i];
     snprintf(buf, sizeof(buf), "|%dx%dx%d", q.M, n_eff_of(q),
@@ -530,63 +191,21 @@ bool lookup(const std::string& key, Plan* out) {
   return true;
 }
 
-// ---- launching ---------------------------------------------------------------
-template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF>
-void launch_cfg(LaunchArgs& args, hipStream_t stream) {
-  int max_tiles = 0;
-  for (int i = 0; i < args.n_prob; ++i) {
-    args.p[i].tiles_m = (int)ceil_div(args.p[i].M, BM);
-    args.p[i].tiles_n = (int)ceil_div(args.p[i].N > 0 ? args.p[i].N : (args.p[i].bias_grad ? 1 : 0), BN);
-    max_tiles = max(max_tiles, args.p[i].tiles_m * args.p[i].tiles_n);
-  }
-  dim3 grid;
-  if (args.splits == 1) {
-    args.grid_x = (int)ceil_div(max_tiles, 8) * 8;
-    grid = dim3(args.grid_x, args.n_prob);
-  } else {
-    args.grid_x = max_tiles;  // tiles per (problem, split) group
-    const int64_t groups = (int64_t)args.n_prob * args.splits;
-    grid = dim3((unsigned)(ceil_div(groups, 8) * 8 * max_tiles));
-  }
-  hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T, PF>), grid, dim3(64 * WM * WN), 0,
-                     stream, args);
-}
-
-template <bool A_T, bool B_T>
-void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
-  switch (cfg) {
-#define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
-  case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF>(args, stream); break;
-    CPRA_GEMM_CFG(0, 64, 64, 32, 2, 2, 1)
-    CPRA_GEMM_CFG(1, 64, 64, 32, 2, 1, 1)
-    CPRA_GEMM_CFG(2, 64, 64, 32, 1, 1, 1)
-    CPRA_GEMM_CFG(3, 128, 64, 32, 2, 2, 1)
-    CPRA_GEMM_CFG(4, 64, 128, 32, 2, 2, 1)
-    CPRA_GEMM_CFG(5, 128, 128, 32, 2, 2, 1)
-    CPRA_GEMM_CFG(6, 64, 64, 16, 2, 2, 1)
-    CPRA_GEMM_CFG(7, 128, 128, 16, 2, 2, 1)
-    CPRA_GEMM_CFG(8, 32, 64, 32, 1, 1, 1)
-    CPRA_GEMM_CFG(9, 64, 32, 32, 1, 1, 1)
-    CPRA_GEMM_CFG(10, 64, 64, 16, 2, 2, 2)
-    CPRA_GEMM_CFG(11, 64, 64, 32, 2, 2, 2)
-    CPRA_GEMM_CFG(12, 128, 64, 16, 2, 2, 2)
-    CPRA_GEMM_CFG(13, 64, 128, 16, 2, 2, 2)
-    CPRA_GEMM_CFG(14, 128, 128, 16, 2, 2, 2)
-    CPRA_GEMM_CFG(15, 64, 32, 16, 1, 1, 2)
-    CPRA_GEMM_CFG(16, 32, 64, 16, 1, 1, 2)
-    CPRA_GEMM_CFG(17, 64, 64, 16, 1, 1, 2)
-    CPRA_GEMM_CFG(18, 64, 64, 16, 2, 1, 2)
-    CPRA_GEMM_CFG(19, 128, 64, 16, 2, 1, 2)
-#undef CPRA_GEMM_CFG
-    default: break;
-  }
-}
-
 void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs* args) {
   *args = LaunchArgs{};
+  const GemmProblem& q0 = probs[0];
   args->n_prob = n;
   args->splits = splits;
   args->partial = static_cast<float*>(ws);
+  args->G = q0.group_mode == 2 ? groups_of(q0) : 1;
+  args->n_vprob = n * args->G;
+  args->gptr = q0.group_ptr;
+  if (q0.group_mode == 1) {
+    for (int b = 0; b < 3; ++b) {
+      args->row_maps[b] = q0.rows->map[b];
+      args->row_counts[b] = q0.rows->count[b];
+    }
+  }
   int64_t off = 0;
   for (int i = 0; i < n; ++i) {
     const GemmProblem& q = probs[i];
@@ -600,7 +219,7 @@ void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs
       d.ldb[pc] = g.ldb;
       d.K[pc] = pc < q.n_pieces ? g.K : 0;
       d.vecA[pc] = vec_ok(g.A, g.lda);
-      d.vecB[pc] = vec_ok(g.B, g.ldb);
+      d.vecB[pc] = vec_ok(g.B, g.ldb) && q.b_stride % 4 == 0;
     }
     d.C = q.C;
     d.ldc = q.ldc;
@@ -616,9 +235,13 @@ void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs
     d.add = q.add;
     d.ld_add = q.ld_add;
     d.ld_sig = q.ld_sig;
+    d.b_stride = q.b_stride;
+    d.c_stride = q.c_stride;
+    d.bias_stride = q.bias_stride;
+    d.bg_stride = q.bg_stride;
     d.n_eff = n_eff_of(q);
     d.part_off = off;
-    off += (int64_t)splits * q.M * d.n_eff;
+    off += (int64_t)splits * args->G * q.M * d.n_eff;
   }
 }
 
@@ -630,23 +253,26 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
   for (int i = 0; i < n; ++i) {
     const double mn = (double)args.p[i].M * args.p[i].N;
     flops += 2.0 * mn * ((double)args.p[i].K[0] + (args.p[i].n_pieces > 1 ? args.p[i].K[1] : 0));
-    red_bytes += 4.0 * (double)args.p[i].M * args.p[i].n_eff * (pl.splits + 1);
+    red_bytes += 4.0 * (double)args.G * args.p[i].M * args.p[i].n_eff * (pl.splits + 1);
   }
-  // profiler family = one kernel instantiation: layout + tile configuration
+  // profiler family = one kernel instantiation: layout + group mode + tile configuration
   static const char* layout[2][2] = {{"nn", "nt"}, {"tn", "tt"}};
+  static const char* gmode[3] = {"", "_byrow", "_byk"};
+  const int mode = probs[0].group_mode;
   char pname[64];
-  snprintf(pname, sizeof(pname), "gemm_%s_%s", layout[a_t][b_t], kCfgNames[pl.cfg]);
+  snprintf(pname, sizeof(pname), "gemm_%s%s_%s", layout[a_t][b_t], gmode[mode], kCfgNames[pl.cfg]);
   {
     ProfScope ps(pname, stream, flops, 0.0);
-    if (!a_t && b_t) launch_any<false, true>(pl.cfg, args, stream);
-    else if (!a_t && !b_t) launch_any<false, false>(pl.cfg, args, stream);
-    else if (a_t && !b_t) launch_any<true, false>(pl.cfg, args, stream);
-    else launch_any<true, true>(pl.cfg, args, stream);
+    if (mode) launch_grouped(mode, a_t, b_t, pl.cfg, args, stream);
+    else if (!a_t && b_t) launch_any<false, true, 0>(pl.cfg, args, stream);
+    else if (!a_t && !b_t) launch_any<false, false, 0>(pl.cfg, args, stream);
+    else if (a_t && !b_t) launch_any<true, false, 0>(pl.cfg, args, stream);
+    else launch_any<true, true, 0>(pl.cfg, args, stream);
   }
   CPRA_CHECK_LAUNCH("gemm");
   if (pl.splits > 1) {
     int64_t maxel = 0;
-    for (int i = 0; i < n; ++i) maxel = max(maxel, (int64_t)args.p[i].M * args.p[i].n_eff);
+    for (int i = 0; i < n; ++i) maxel = max(maxel, (int64_t)args.G * args.p[i].M * args.p[i].n_eff);
     {
       ProfScope ps("gemm_splitk_reduce", stream, 0.0, red_bytes);
       hipLaunchKernelGGL(k_gemm_splitk_reduce, dim3(ceil_div(maxel, kRedElems), n),
@@ -725,9 +351,34 @@ size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, 
   return best;
 }
 
-cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws,
+cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs_in, int n, void* ws,
                        size_t ws_bytes, hipStream_t stream) {
   if (n < 1 || n > kMaxProblems) CPRA_FAIL(CPRA_ERR_PARAM, "gemm: 1..4 problems per launch");
+  GemmProblem local[kMaxProblems];
+  const GemmProblem* probs = probs_in;
+  if (probs_in[0].group_mode) {
+    const GemmProblem& q0 = probs_in[0];
+    for (int i = 0; i < n; ++i) {
+      const GemmProblem& q = probs_in[i];
+      if (q.group_mode != q0.group_mode || q.n_groups != q0.n_groups || q.group_ptr != q0.group_ptr ||
+          q.rows != q0.rows)
+        CPRA_FAIL(CPRA_ERR_PARAM, "gemm: the problems of a launch must share their grouping");
+      if (q.group_mode == 1 && (a_t || q.bias_grad || (q.n_groups > 1 && q.rows == nullptr)))
+        CPRA_FAIL(CPRA_ERR_PARAM, "gemm: row-grouped products take A [rows, K], no bias gradient, a row map");
+      if (q.group_mode == 2 && (!a_t || b_t || q.bias || q.mask || q.add || q.sig_out || q.beta != 0.f ||
+                                q.relu || (q.n_groups > 1 && q.group_ptr == nullptr)))
+        CPRA_FAIL(CPRA_ERR_PARAM, "gemm: K-grouped products are plain A^T B with a graph row map");
+      if (q.group_mode != 1 && q.group_mode != 2)
+        CPRA_FAIL(CPRA_ERR_PARAM, "gemm: group mode %d", q.group_mode);
+    }
+    if (q0.n_groups <= 1) {  // one graph: the plain product
+      for (int i = 0; i < n; ++i) {
+        local[i] = probs_in[i];
+        local[i].group_mode = 0;
+      }
+      probs = local;
+    }
+  }
   for (int i = 0; i < n; ++i)
     if (probs[i].bias_grad && probs[i].bias)
       CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad and bias are exclusive");
@@ -750,7 +401,8 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void
     pl = heuristic_plan(probs, n, can_split);
   }
   // A tuned plan may split more than this workspace allows: fall back to fewer splits.
-  if (!can_split) pl.splits = 1;
+  // Row-grouped products are never split (their reduction has no per-graph bias).
+  if (!can_split || probs[0].group_mode == 1) pl.splits = 1;
   while (pl.splits > 1 && partial_floats(pl.splits, probs, n) * sizeof(float) > ws_bytes)
     pl.splits /= 2;
   return run_plan(a_t, b_t, probs, n, pl, ws, stream);

@@ -1,0 +1,490 @@
+// The FP32 MFMA GEMM kernel template (v_mfma_f32_32x32x2f32), shared by the
+// translation unit of the plain launches (gemm.hip) and that of the launches
+// over the graphs of a block-diagonal batch (gemm_grouped.hip), so that the
+// two sets of instantiations compile in parallel.  Not part of the ABI.
+//
+// A block computes a BM x BN tile with WM x WN wavefronts, each owning
+// TM x TN = (BM/32/WM) x (BN/32/WN) accumulators of 32 x 32.  K advances in
+// BK-deep steps staged through LDS in the [k][mn] layout (double buffered,
+// one barrier per step): the next step's global loads are issued before the
+// current step's MFMAs, all MFMA operands of a step are read from LDS into
+// registers before the first MFMA of the step, and K-contiguous operands are
+// transposed while being written to LDS so every operand read is 32
+// consecutive floats per half-wavefront.  Interior tiles take unguarded
+// float4 loads (a uniform branch); edge tiles fall back to guarded loads.
+//
+// Group modes (GM) for batches with one weight set per graph, graph g owning
+// rows gptr[g] .. gptr[g+1]-1 of the batch:
+//  GM = 1 (by rows): C[rows of g] = A[rows of g] op(B_g) (+ bias_g) with
+//         B_g = B + g * b_stride and bias_g = bias + g * bias_stride.  Row
+//         tiles never cross a graph boundary: a precomputed map gives each
+//         row tile's graph, first row and end row;
+//  GM = 2 (by K): C_g = A[rows of g]^T B[rows of g] at C + g * c_stride (and
+//         the bias gradient of graph g at bias_grad + g * bg_stride): the
+//         contraction runs over the graph's rows only.
+#pragma once
+
+#include "common.hpp"
+
+namespace cpra {
+namespace gemmk {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMaxProblems = 4;
+
+struct ProbDev {
+  const float* A[2];
+  const float* B[2];
+  int64_t lda[2], ldb[2];
+  int K[2];
+  int vecA[2], vecB[2];
+  int n_pieces;
+  float* C;
+  int64_t ldc;
+  int M, N;
+  const float* bias;
+  const float* mask;
+  int64_t ld_mask;
+  float beta;
+  int relu;
+  float* bias_grad;  // [M] row sums of op(A) over K (computed by the first column tile), or null
+  float* sig_out;    // [M, N] (ld_sig): sigmoid of the result, or null
+  int64_t ld_sig;
+  const float* add;  // [M, N] (ld_add): extra addend, or null
+  int64_t ld_add;
+  int64_t b_stride, c_stride, bias_stride, bg_stride;  // per-graph offsets (group modes)
+  int n_eff;         // N + 1 when bias_grad is set
+  int tiles_m, tiles_n;
+  int64_t part_off;  // float offset of this problem's split-K partials
+};
+
+struct LaunchArgs {
+  ProbDev p[kMaxProblems];
+  int n_prob;
+  int n_vprob;  // problems x graphs in mode 2, else n_prob
+  int splits;
+  int grid_x;   // 2-D grid: blocks per problem (a multiple of 8); 1-D grid: tiles per group
+  float* partial;
+  int G;                   // graphs (mode 2: C / partial sets per problem); 1 otherwise
+  const int32_t* gptr;     // [G + 1] graph row offsets (mode 2)
+  const int4* row_map;     // mode 1: per row tile {graph, first row, end row, 0}; graph -1: none
+  const int4* row_maps[3];  // the maps for BM = 32, 64, 128 (the launcher picks row_map)
+  int row_counts[3];
+};
+
+// One operand tile [BK][R] in LDS, loaded by NT threads as float4 vectors.
+template <int R, int BK, int NT, bool KCONTIG>
+struct Tile {
+  static constexpr int PAD = KCONTIG ? 1 : 4;
+  static constexpr int LD = R + PAD;  // LDS row stride (floats)
+  static constexpr int NV = R * BK / 4 / NT;
+  static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
+  float4 reg[NV];
+
+  __device__ inline void load(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim, int k0,
+                              int k_lim, bool vec_ok, int tid) {
+    const bool full = vec_ok && (mn0 + R <= mn_lim) && (k0 + BK <= k_lim);
+    if (full) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int idx = tid + v * NT;
+        if constexpr (KCONTIG) {
+          const int r = idx / (BK / 4);
+          const int kq = (idx % (BK / 4)) * 4;
+          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(mn0 + r) * ld + k0 + kq);
+        } else {
+          const int k = idx / (R / 4);
+          const int rq = (idx % (R / 4)) * 4;
+          reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)(k0 + k) * ld + mn0 + rq);
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      if constexpr (KCONTIG) {
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        const int gm = mn0 + r, gk = k0 + kq;
+        const bool rok = gm < mn_lim;
+        const float* p = X + (int64_t)(rok ? gm : 0) * ld;
+        reg[v].x = (rok && gk + 0 < k_lim) ? p[gk + 0] : 0.f;
+        reg[v].y = (rok && gk + 1 < k_lim) ? p[gk + 1] : 0.f;
+        reg[v].z = (rok && gk + 2 < k_lim) ? p[gk + 2] : 0.f;
+        reg[v].w = (rok && gk + 3 < k_lim) ? p[gk + 3] : 0.f;
+      } else {
+        const int k = idx / (R / 4);
+        const int rq = (idx % (R / 4)) * 4;
+        const int gk = k0 + k, gm = mn0 + rq;
+        const bool kok = gk < k_lim;
+        const float* p = X + (int64_t)(kok ? gk : 0) * ld;
+        reg[v].x = (kok && gm + 0 < mn_lim) ? p[gm + 0] : 0.f;
+        reg[v].y = (kok && gm + 1 < mn_lim) ? p[gm + 1] : 0.f;
+        reg[v].z = (kok && gm + 2 < mn_lim) ? p[gm + 2] : 0.f;
+        reg[v].w = (kok && gm + 3 < mn_lim) ? p[gm + 3] : 0.f;
+      }
+    }
+  }
+
+  __device__ inline void store(float* __restrict__ Xs, int tid) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      if constexpr (KCONTIG) {
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        Xs[(kq + 0) * LD + r] = reg[v].x;
+        Xs[(kq + 1) * LD + r] = reg[v].y;
+        Xs[(kq + 2) * LD + r] = reg[v].z;
+        Xs[(kq + 3) * LD + r] = reg[v].w;
+      } else {
+        const int k = idx / (R / 4);
+        const int rq = (idx % (R / 4)) * 4;
+        *reinterpret_cast<float4*>(Xs + k * LD + rq) = reg[v];
+      }
+    }
+  }
+};
+
+
+// C[row, col] = mask(relu(v + add + beta C)) and optionally sigmoid(C) into sig_out.
+__device__ inline void epilogue_store(const ProbDev& P, float* C, int row, int col, float v) {
+  float* cp = C + (int64_t)row * P.ldc + col;
+  if (P.add) v += P.add[(int64_t)row * P.ld_add + col];
+  if (P.beta != 0.f) v += P.beta * *cp;
+  if (P.relu) v = fmaxf(v, 0.f);
+  if (P.mask && !(P.mask[(int64_t)row * P.ld_mask + col] > 0.f)) v = 0.f;
+  *cp = v;
+  if (P.sig_out) {
+    const float e = expf(-fabsf(v));
+    const float r = 1.0f / (1.0f + e);
+    P.sig_out[(int64_t)row * P.ld_sig + col] = v >= 0.0f ? r : e * r;
+  }
+}
+
+// A_T: A stored [K, M] (M contiguous); otherwise [M, K].
+// B_T: B stored [N, K] (K contiguous); otherwise [K, N].
+// PF: prefetch distance in K tiles (1: the next tile is loaded while the
+// current one is multiplied; 2: two tiles ahead, in two register sets, so a
+// load has two K steps of MFMA work to land).
+// GM: group mode (0 none, 1 by rows, 2 by K).
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF, int GM>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / (32 * WM);  // 32x32 accumulators per wave along M
+  constexpr int TN = BN / (32 * WN);
+  static_assert(TM >= 1 && TN >= 1 && TM * 32 * WM == BM && TN * 32 * WN == BN, "bad tiling");
+  using TA = Tile<BM, BK, NT, !A_T>;
+  using TB = Tile<BN, BK, NT, B_T>;
+  __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
+
+  // XCD-aware order: the hardware deals consecutive block ids round-robin to
+  // the 8 XCDs, each with its own L2.
+  //  * 2-D grid (tiles x problems; no split, modes 0 and 1): each XCD gets a
+  //    contiguous run of tiles, so neighbouring N tiles share their A panel in
+  //    that XCD's L2;
+  //  * 1-D grid (split-K, or mode 2): all tiles of one (problem, graph, split)
+  //    group -- which read the same K rows of A and B -- go to the same XCD.
+  int vp, split, tile;
+  if (GM != 2 && args.splits == 1) {
+    vp = blockIdx.y;
+    split = 0;
+    const int per_xcd = args.grid_x / 8;
+    tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  } else {
+    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int group = x + 8 * (j / args.grid_x);  // grid_x = tiles per group here
+    tile = j % args.grid_x;
+    if (group >= args.n_vprob * args.splits) return;
+    vp = group / args.splits;
+    split = group % args.splits;
+  }
+  int prob = vp, grp = 0;
+  if constexpr (GM == 2) {
+    prob = vp / args.G;
+    grp = vp - prob * args.G;
+  }
+  const ProbDev& P = args.p[prob];
+  if (tile >= P.tiles_m * P.tiles_n) return;
+  const int tm_idx = tile / P.tiles_n;
+  const int tn_idx = tile % P.tiles_n;
+  int m0 = tm_idx * BM;
+  const int n0 = tn_idx * BN;
+
+  // operands, limits and outputs of this block's (problem, graph)
+  int m_lim = P.M;
+  int kb = 0, kn0 = P.K[0], kn1 = P.K[1];
+  int64_t b_off = 0;
+  float* Cg = P.C;
+  const float* bias_g = P.bias;
+  float* bgrad_g = P.bias_grad;
+  bool vA0 = P.vecA[0] != 0, vA1 = P.vecA[1] != 0, vB0 = P.vecB[0] != 0, vB1 = P.vecB[1] != 0;
+  if constexpr (GM == 1) {
+    const int4 e = args.row_map[tm_idx];
+    if (e.x < 0) return;  // past the last row tile of the batch
+    m0 = e.y;
+    m_lim = e.z;
+    b_off = (int64_t)e.x * P.b_stride;
+    if (bias_g) bias_g += (int64_t)e.x * P.bias_stride;
+  } else if constexpr (GM == 2) {
+    kb = args.gptr[grp];
+    const int kn = args.gptr[grp + 1] - kb;
+    kn0 = kn;
+    kn1 = P.n_pieces > 1 ? kn : 0;
+    Cg += (int64_t)grp * P.c_stride;
+    if (bgrad_g) bgrad_g += (int64_t)grp * P.bg_stride;
+    if (kb & 3) {  // K-contiguous operands lose their float4 alignment at this offset
+      if (!A_T) vA0 = vA1 = false;
+      if (B_T) vB0 = vB1 = false;
+    }
+  }
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int half = lane >> 5, l32 = lane & 31;
+
+  const int nt0 = (kn0 + BK - 1) / BK;
+  const int nt1 = P.n_pieces > 1 ? (kn1 + BK - 1) / BK : 0;
+  const int KT = nt0 + nt1;
+  const int per_split = (KT + args.splits - 1) / args.splits;
+  const int kt_begin = min(KT, split * per_split);
+  const int kt_end = min(KT, kt_begin + per_split);
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  auto load_into = [&](TA& ta, TB& tb, int kt) {
+    const int pc = kt < nt0 ? 0 : 1;
+    const int k0 = kb + (kt - (pc ? nt0 : 0)) * BK;
+    const int kl = kb + (pc ? kn1 : kn0);
+    ta.load(P.A[pc], P.lda[pc], m0, m_lim, k0, kl, pc ? vA1 : vA0, tid);
+    tb.load(P.B[pc] + b_off, P.ldb[pc], n0, P.N, k0, kl, pc ? vB1 : vB0, tid);
+  };
+  // Bias gradient (row sums of op(A) over this block's K range): the blocks of
+  // the first column tile add up the staged A tile with plain VALU adds, thread
+  // t owning row t % BM and a fixed slice of each tile's BK rows (zero padding
+  // outside the matrix is already in the tile).
+  constexpr int BG = NT / BM > 0 ? NT / BM : 1;  // threads per row
+  static_assert(BK % BG == 0, "bias slice");
+  const bool do_bias = bgrad_g != nullptr && tn_idx == 0;
+  const int b_row = tid % BM, b_grp = tid / BM;
+  float bsum = 0.f;
+
+  // multiply the tile staged in LDS buffer `cur` (and add its A rows for the bias)
+  auto compute = [&](int cur) {
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+    if (do_bias && b_grp < BG) {
+#pragma unroll
+      for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
+    }
+    float af[BK / 2][TM], bf[BK / 2][TN];
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kr = 2 * kk + half;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
+  };
+
+  if constexpr (PF == 1) {
+    TA ta;
+    TB tb;
+    if (kt_begin < kt_end) {
+      load_into(ta, tb, kt_begin);
+      ta.store(As[0], tid);
+      tb.store(Bs[0], tid);
+      __syncthreads();
+      for (int kt = kt_begin; kt < kt_end; ++kt) {
+        const int cur = (kt - kt_begin) & 1;
+        const bool more = kt + 1 < kt_end;
+        if (more) load_into(ta, tb, kt + 1);
+        compute(cur);
+        if (more) {
+          ta.store(As[cur ^ 1], tid);
+          tb.store(Bs[cur ^ 1], tid);
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    // Two register sets; the loop is unrolled by two so that every set is
+    // named statically.  In the body for tile kt: LDS[cur] holds tile kt, set
+    // `nxt` holds tile kt + 1 (stored to LDS[cur ^ 1] at the end), and set
+    // `fre` (whose tile kt is already in LDS) receives tile kt + 2.
+    TA ta0, ta1;
+    TB tb0, tb1;
+    auto body = [&](int kt, int cur, TA& fre_a, TB& fre_b, TA& nxt_a, TB& nxt_b) {
+      if (kt + 2 < kt_end) load_into(fre_a, fre_b, kt + 2);
+      compute(cur);
+      if (kt + 1 < kt_end) {
+        nxt_a.store(As[cur ^ 1], tid);
+        nxt_b.store(Bs[cur ^ 1], tid);
+      }
+      __syncthreads();
+    };
+    if (kt_begin < kt_end) {
+      load_into(ta0, tb0, kt_begin);
+      ta0.store(As[0], tid);
+      tb0.store(Bs[0], tid);
+      if (kt_begin + 1 < kt_end) load_into(ta1, tb1, kt_begin + 1);
+      __syncthreads();
+      for (int kt = kt_begin; kt < kt_end; kt += 2) {
+        body(kt, 0, ta0, tb0, ta1, tb1);
+        if (kt + 1 < kt_end) body(kt + 1, 1, ta1, tb1, ta0, tb0);
+      }
+    }
+  }
+
+  // Accumulator layout of the 32x32 MFMA: register r of lane l holds
+  // D[8*(r/4) + 4*(l/32) + r%4][l%32].
+  const bool partial = args.splits > 1;
+  const int GE = GM == 2 ? args.G : 1;
+  float* part = partial
+                    ? args.partial + P.part_off + ((int64_t)split * GE + grp) * P.M * P.n_eff
+                    : nullptr;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + (wn * TN + j) * 32 + l32;
+      if (col >= P.N) continue;
+      const float bv = (!partial && bias_g) ? bias_g[col] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + (wm * TM + i) * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
+        if (row >= m_lim) continue;
+        const float v = acc[i][j][r];
+        if (partial) {
+          part[(int64_t)row * P.n_eff + col] = v;
+        } else {
+          epilogue_store(P, Cg, row, col, v + bv);
+        }
+      }
+    }
+  }
+  if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
+    float* red = As[0];
+    if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
+    __syncthreads();
+    if (tid < BM && m0 + tid < m_lim) {
+      float v = 0.f;
+      for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
+      if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
+      else bgrad_g[m0 + tid] = v;
+    }
+  }
+}
+
+// ---- configurations -------------------------------------------------------
+struct Cfg {
+  int bm, bn, bk, wm, wn;
+};
+constexpr Cfg kCfgs[] = {
+    {64, 64, 32, 2, 2},    // 0: 256 threads, one 32x32 accumulator per wave
+    {64, 64, 32, 2, 1},    // 1: 128 threads, 32x64 per wave
+    {64, 64, 32, 1, 1},    // 2: 64 threads, 64x64 per wave
+    {128, 64, 32, 2, 2},   // 3: 256 threads, 64x32 per wave
+    {64, 128, 32, 2, 2},   // 4: 256 threads, 32x64 per wave
+    {128, 128, 32, 2, 2},  // 5: 256 threads, 64x64 per wave
+    {64, 64, 16, 2, 2},    // 6
+    {128, 128, 16, 2, 2},  // 7
+    {32, 64, 32, 1, 1},    // 8: 64 threads, 32x64 per wave
+    {64, 32, 32, 1, 1},    // 9: 64 threads, 64x32 per wave
+    // prefetch distance 2 (tiles loaded two K steps ahead)
+    {64, 64, 16, 2, 2},    // 10
+    {64, 64, 32, 2, 2},    // 11
+    {128, 64, 16, 2, 2},   // 12
+    {64, 128, 16, 2, 2},   // 13
+    {128, 128, 16, 2, 2},  // 14
+    // prefetch distance 2 with more than one accumulator per wave (fewer, busier waves)
+    {64, 32, 16, 1, 1},    // 15: 64 threads, 64x32 per wave
+    {32, 64, 16, 1, 1},    // 16: 64 threads, 32x64 per wave
+    {64, 64, 16, 1, 1},    // 17: 64 threads, 64x64 per wave
+    {64, 64, 16, 2, 1},    // 18: 128 threads, 32x64 per wave
+    {128, 64, 16, 2, 1},   // 19: 128 threads, 64x64 per wave
+};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+// index of a row-tile height in LaunchArgs::row_maps
+constexpr int bm_index(int bm) { return bm == 32 ? 0 : bm == 64 ? 1 : 2; }
+
+// ---- launching ---------------------------------------------------------------
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF, int GM>
+void launch_cfg(LaunchArgs& args, hipStream_t stream) {
+  int max_tiles = 0;
+  for (int i = 0; i < args.n_prob; ++i) {
+    ProbDev& d = args.p[i];
+    d.tiles_m = GM == 1 ? args.row_counts[bm_index(BM)] : (int)ceil_div(d.M, BM);
+    d.tiles_n = (int)ceil_div(d.N > 0 ? d.N : (d.bias_grad ? 1 : 0), BN);
+    max_tiles = max(max_tiles, d.tiles_m * d.tiles_n);
+  }
+  if (GM == 1) args.row_map = args.row_maps[bm_index(BM)];
+  dim3 grid;
+  if (GM != 2 && args.splits == 1) {
+    args.grid_x = (int)ceil_div(max_tiles, 8) * 8;
+    grid = dim3(args.grid_x, args.n_prob);
+  } else {
+    args.grid_x = max_tiles;  // tiles per (problem, graph, split) group
+    const int64_t groups = (int64_t)args.n_vprob * args.splits;
+    grid = dim3((unsigned)(ceil_div(groups, 8) * 8 * max_tiles));
+  }
+  hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>), grid, dim3(64 * WM * WN), 0,
+                     stream, args);
+}
+
+template <bool A_T, bool B_T, int GM>
+void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
+  switch (cfg) {
+#define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
+  case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream); break;
+    CPRA_GEMM_CFG(0, 64, 64, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(1, 64, 64, 32, 2, 1, 1)
+    CPRA_GEMM_CFG(2, 64, 64, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(3, 128, 64, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(4, 64, 128, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(5, 128, 128, 32, 2, 2, 1)
+    CPRA_GEMM_CFG(6, 64, 64, 16, 2, 2, 1)
+    CPRA_GEMM_CFG(7, 128, 128, 16, 2, 2, 1)
+    CPRA_GEMM_CFG(8, 32, 64, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(9, 64, 32, 32, 1, 1, 1)
+    CPRA_GEMM_CFG(10, 64, 64, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(11, 64, 64, 32, 2, 2, 2)
+    CPRA_GEMM_CFG(12, 128, 64, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(13, 64, 128, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(14, 128, 128, 16, 2, 2, 2)
+    CPRA_GEMM_CFG(15, 64, 32, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(16, 32, 64, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(17, 64, 64, 16, 1, 1, 2)
+    CPRA_GEMM_CFG(18, 64, 64, 16, 2, 1, 2)
+    CPRA_GEMM_CFG(19, 128, 64, 16, 2, 1, 2)
+#undef CPRA_GEMM_CFG
+    default: break;
+  }
+}
+
+// Launchers of the group modes (defined in gemm_grouped.hip): mode 1 for the
+// NN and NT layouts, mode 2 for TN.
+void launch_grouped(int mode, bool a_t, bool b_t, int cfg, LaunchArgs& args, hipStream_t stream);
+
+}  // namespace gemmk
+}  // namespace cpra

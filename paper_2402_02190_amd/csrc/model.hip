@@ -18,6 +18,14 @@
 // its epilogue, for the loss.  M^T = A D^-1 is applied by the transposed
 // aggregation (not M: the graph need not be regular).  With recompute set,
 // AX is not kept from the forward and is rebuilt in the backward.
+//
+// Per-graph weights (weight_groups = G > 1): every weight product becomes a
+// grouped GEMM over the batch's graphs -- the forward and input-gradient
+// products by rows (graph g's rows times graph g's weights), the weight
+// gradients by K (graph g's weight gradient sums over graph g's rows only).
+// The aggregations are unchanged (the batch is block-diagonal), and in the
+// linear-first order the bias moves into the self-weight GEMM's epilogue
+// (it is graph g's bias for graph g's rows).
 #include <algorithm>
 
 #include "common.hpp"
@@ -38,6 +46,7 @@ struct Layer {
 };
 
 struct Plan {
+  int G;                  // weight sets (1: shared by all graphs)
   const float* z_offset;  // [N, S] added to the output layer, or null
   int train_from;         // first trained layer (0: all, embedding included)
   bool reuse_prefix;      // forward starts at train_from from saved activations
@@ -49,7 +58,7 @@ struct Plan {
   size_t h_off[kMaxLayers];   // saved input of layer k (k >= 1)
   size_t ax_off[kMaxLayers];  // saved M H of aggregate-first layers
   size_t ax_scratch_off;      // recompute buffer
-  size_t yy_off, d_off[2], g_off, t_off, p_off, gemm_off;
+  size_t yy_off, d_off[2], g_off, t_off, p_off, gemm_off, rows_off;
   size_t gemm_bytes;
   size_t total;
 };
@@ -69,10 +78,12 @@ cpra_status check_model_cfg(const cpra_model_cfg* cfg) {
     CPRA_FAIL(CPRA_ERR_PARAM, "model: widths must be >= 1 and S <= 1024");
   if (cfg->in_dim > 4096 || cfg->hidden > 4096)
     CPRA_FAIL(CPRA_ERR_PARAM, "model: in_dim and hidden up to 4096 supported");
+  if (cfg->weight_groups < 0) CPRA_FAIL(CPRA_ERR_PARAM, "model: weight_groups < 0");
   return CPRA_OK;
 }
 
 void make_layers(const cpra_model_cfg* cfg, int N, Plan* p) {
+  p->G = std::max(cfg->weight_groups, 1);
   p->L = cfg->n_layers;
   p->sage = cfg->layer_kind == CPRA_SAGE;
   p->recompute = cfg->recompute != 0;
@@ -85,18 +96,32 @@ void make_layers(const cpra_model_cfg* cfg, int N, Plan* p) {
     l.out = (k == p->L - 1) ? cfg->S : cfg->hidden;
     l.lf = l.out < l.in;
     l.off_ws = off;
-    off += (int64_t)l.out * l.in;
+    off += (int64_t)p->G * l.out * l.in;
     l.off_wn = off;
-    off += (int64_t)l.out * l.in;
+    off += (int64_t)p->G * l.out * l.in;
     if (p->sage) {
       l.off_b = off;
-      off += l.out;
+      off += (int64_t)p->G * l.out;
     } else {
       l.off_b = -1;
     }
     d_in = l.out;
   }
   p->n_params = off;
+}
+
+// Per-graph grouping of a GEMM (no-op with shared weights).
+void set_groups(const Plan& p, const cpra_csr* g, const GroupRows* rows, int mode, GemmProblem* q,
+                const Layer& l) {
+  if (p.G <= 1) return;
+  q->group_mode = mode;
+  q->n_groups = p.G;
+  q->group_ptr = g ? g->graph_ptr : nullptr;
+  q->rows = rows;
+  q->b_stride = (int64_t)l.out * l.in;  // one Ws / Wn copy
+  q->c_stride = (int64_t)l.out * l.in;
+  q->bias_stride = l.out;
+  q->bg_stride = l.out;
 }
 
 // Weight-gradient GEMM shapes of layer k (for the workspace query).
@@ -108,11 +133,13 @@ void wgrad_problems(const Plan& p, int k, GemmProblem* q) {
     q[i].piece[0].K = p.N;
     q[i].M = l.out;
     q[i].N = l.in;
+    set_groups(p, nullptr, nullptr, 2, &q[i], l);
   }
   if (p.sage) q[0].bias_grad = reinterpret_cast<float*>(1);  // shape only: one extra column
 }
 
-void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
+void make_plan(const cpra_model_cfg* cfg, const cpra_csr* g, Plan* p) {
+  const int N = g->n_nodes;
   make_layers(cfg, N, p);
   p->z_offset = cfg->z_offset;
   p->train_from = cfg->train_from_layer;
@@ -152,6 +179,7 @@ void make_plan(const cpra_model_cfg* cfg, int N, Plan* p) {
   }
   p->gemm_bytes = gb;
   p->gemm_off = gb ? take(gb) : 0;
+  p->rows_off = p->G > 1 ? take(group_rows_bytes(g)) : 0;
   p->total = std::max<size_t>(off, 256);
 }
 
@@ -162,6 +190,8 @@ inline float* fptr(void* ws, size_t off) {
 cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, float* Z,
                          int64_t ldz, void* ws, hipStream_t st) {
   const int N = g->n_nodes;
+  GroupRows rows{};
+  if (p.G > 1) CPRA_CHECK(group_rows_build(g, static_cast<char*>(ws) + p.rows_off, &rows, st));
   // With a reused frozen prefix the forward starts at the first trained layer,
   // from the input the previous forward saved.
   const int k0 = p.reuse_prefix ? p.train_from : 0;
@@ -197,6 +227,7 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
         q.add = p.z_offset;
         q.ld_add = l.out;
       }
+      set_groups(p, g, &rows, 1, &q, l);
       CPRA_CHECK(gemm_batch(false, true, &q, 1, nullptr, 0, st));
     } else {
       float* YY = fptr(ws, p.yy_off);
@@ -209,10 +240,13 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
         q[i].ldc = ldyy;
         q[i].M = N;
         q[i].N = l.out;
+        set_groups(p, g, &rows, 1, &q[i], l);
       }
+      // per-graph biases are added by the self-weight GEMM (graph g's bias on graph g's rows)
+      if (p.G > 1) q[0].bias = b;
       CPRA_CHECK(gemm_batch(false, true, q, 2, nullptr, 0, st));
-      CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, b, !last, nullptr,
-                           0, st, P, l.out, last ? p.z_offset : nullptr, l.out));
+      CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, p.G > 1 ? nullptr : b,
+                           !last, nullptr, 0, st, P, l.out, last ? p.z_offset : nullptr, l.out));
     }
     H = dst;
     ldh = ldd;
@@ -238,10 +272,21 @@ struct PendingReads {
   }
 };
 
+// rows_ready: the row-tile maps of per-graph weights are in ws already (built
+// by the forward of the same step).
 cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params, const float* dZ,
                           int64_t lddz, float* grads, void* ws, hipStream_t st,
-                          SideStream* side) {
+                          SideStream* side, bool rows_ready) {
   const int N = g->n_nodes;
+  GroupRows rows{};
+  if (p.G > 1) {
+    void* rws = static_cast<char*>(ws) + p.rows_off;
+    if (rows_ready) {
+      CPRA_CHECK(group_rows_view(g, rws, &rows));
+    } else {
+      CPRA_CHECK(group_rows_build(g, rws, &rows, st));
+    }
+  }
   const hipStream_t wst = side ? side->stream : st;  // stream of the weight gradients
   PendingReads pending;
   auto before_write = [&](const void* buf) -> cpra_status {
@@ -285,6 +330,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].ldc = l.in;
         q[i].M = l.out;
         q[i].N = l.in;
+        set_groups(p, g, &rows, 2, &q[i], l);
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
@@ -299,6 +345,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       r.N = l.in;
       r.mask = mask;
       r.ld_mask = ldh;
+      set_groups(p, g, &rows, 1, &r, l);
       CPRA_CHECK(before_write(dX));
       CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
     } else {
@@ -322,6 +369,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         q[i].ldc = l.in;
         q[i].M = l.out;
         q[i].N = l.in;
+        set_groups(p, g, &rows, 2, &q[i], l);
       }
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
@@ -336,6 +384,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         r[i].ldc = ldg;
         r[i].M = N;
         r[i].N = l.in;
+        set_groups(p, g, &rows, 1, &r[i], l);
       }
       CPRA_CHECK(gemm_batch(false, false, r, 2, nullptr, 0, st));
       CPRA_CHECK(before_write(dX));
@@ -351,6 +400,9 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
 cpra_status check_graph_and_model(const cpra_csr* g, const cpra_model_cfg* cfg, const char* who) {
   CPRA_CHECK(check_csr(g, who, true, false));
   CPRA_CHECK(check_model_cfg(cfg));
+  if (cfg->weight_groups > 1 && cfg->weight_groups != g->n_graphs)
+    CPRA_FAIL(CPRA_ERR_PARAM, "%s: weight_groups = %d but the graph has %d graphs", who,
+              cfg->weight_groups, g->n_graphs);
   return CPRA_OK;
 }
 
@@ -384,7 +436,7 @@ cpra_status cpra_model_param_offsets(const cpra_model_cfg* cfg, int32_t n_nodes,
 size_t cpra_model_workspace_bytes(const cpra_csr* g, const cpra_model_cfg* cfg) {
   if (g == nullptr || cpra::check_model_cfg(cfg) != CPRA_OK) return 0;
   cpra::Plan p{};
-  cpra::make_plan(cfg, g->n_nodes, &p);
+  cpra::make_plan(cfg, g, &p);
   return p.total;
 }
 
@@ -397,7 +449,7 @@ cpra_status cpra_model_forward(const cpra_csr* g, const cpra_model_cfg* cfg, con
   if (g->n_nodes == 0) return CPRA_OK;
   if (params == nullptr || Z == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "model_forward: NULL buffer");
   Plan p{};
-  make_plan(cfg, g->n_nodes, &p);
+  make_plan(cfg, g, &p);
   if (ws == nullptr || ws_bytes < p.total)
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_forward: workspace %zu < %zu bytes", ws_bytes, p.total);
   return forward_impl(g, p, params, Z, ldz, ws, as_stream(stream));
@@ -413,12 +465,12 @@ cpra_status cpra_model_backward(const cpra_csr* g, const cpra_model_cfg* cfg, co
   if (params == nullptr || dZ == nullptr || grads == nullptr)
     CPRA_FAIL(CPRA_ERR_NULL, "model_backward: NULL buffer");
   Plan p{};
-  make_plan(cfg, g->n_nodes, &p);
+  make_plan(cfg, g, &p);
   if (ws == nullptr || ws_bytes < p.total)
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_backward: workspace %zu < %zu bytes", ws_bytes, p.total);
   SideStream* side = nullptr;
   if (overlap_enabled()) CPRA_CHECK(get_side_stream(&side));
-  CPRA_CHECK(backward_impl(g, p, params, dZ, lddz, grads, ws, as_stream(stream), side));
+  CPRA_CHECK(backward_impl(g, p, params, dZ, lddz, grads, ws, as_stream(stream), side, false));
   if (side) CPRA_CHECK(join_from(side, as_stream(stream)));
   return CPRA_OK;
 }
@@ -432,7 +484,7 @@ cpra_status cpra_model_saved_activation(const cpra_csr* g, const cpra_model_cfg*
   if (layer < 1 || layer >= cfg->n_layers)
     CPRA_FAIL(CPRA_ERR_PARAM, "model_saved_activation: layer %d outside 1..%d", layer, cfg->n_layers - 1);
   Plan p{};
-  make_plan(cfg, g->n_nodes, &p);
+  make_plan(cfg, g, &p);
   if (ws == nullptr || ws_bytes < p.total)
     CPRA_FAIL(CPRA_ERR_WORKSPACE, "model_saved_activation: workspace %zu < %zu bytes", ws_bytes, p.total);
   *out = fptr(ws, p.h_off[layer]);
@@ -443,7 +495,7 @@ cpra_status cpra_model_saved_activation(const cpra_csr* g, const cpra_model_cfg*
 size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg) {
   if (g == nullptr || cfg == nullptr || cpra::check_model_cfg(&cfg->model) != CPRA_OK) return 0;
   cpra::Plan p{};
-  cpra::make_plan(&cfg->model, g->n_nodes, &p);
+  cpra::make_plan(&cfg->model, g, &p);
   return cpra::align_up(p.total, 256) + cpra::loss_workspace_bytes(g, cfg->model.S, false);
 }
 
@@ -465,7 +517,7 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   if (g->n_nodes == 0) return CPRA_OK;
   if (!params || !grads || !m || !v || !Z || !dZ) CPRA_FAIL(CPRA_ERR_NULL, "train_step: NULL buffer");
   Plan p{};
-  make_plan(&cfg->model, g->n_nodes, &p);
+  make_plan(&cfg->model, g, &p);
   const size_t model_bytes = align_up(p.total, 256);
   const size_t need = model_bytes + loss_workspace_bytes(g, cfg->model.S, false);
   if (ws == nullptr || ws_bytes < need)
@@ -487,7 +539,7 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   } else if (step_counter) {
     CPRA_CHECK(increment_counter(step_counter, st));
   }
-  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side));
+  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side, true));
   if (side) CPRA_CHECK(join_from(side, st));
   // only the trainable tail [first trained layer, end) when the encoder is frozen
   const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : 0;

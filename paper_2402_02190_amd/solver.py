@@ -42,6 +42,7 @@ class CPRAConfig:
     weight_decay: float = 0.0
     recompute: bool = False
     train_from_layer: int = 0  # > 0: layers below (and the embedding) are frozen
+    per_graph_weights: bool = False  # batches: every graph its own layer weights
 
 
 def gamma_schedule(t: int, T: int, g0: float, g1: float) -> float:
@@ -69,9 +70,12 @@ class CPRASolver:
         if z_offset is not None and tuple(z_offset.shape) != (N, S):
             raise ValueError(f"z_offset must be [{N}, {S}]")
         self.z_offset = z_offset
+        # weight sets: one per graph of the batch, or one shared (reported as 0)
+        self.G = graph.n_graphs if cfg.per_graph_weights and graph.n_graphs > 1 else 0
         self.model_cfg = api.make_model_cfg(api.SAGE if cfg.layer_kind == "sage" else api.GCN,
                                             cfg.n_layers, in_dim, cfg.hidden, S, cfg.recompute,
-                                            z_offset, cfg.train_from_layer)
+                                            z_offset, cfg.train_from_layer,
+                                            weight_groups=self.G)
         if cfg.problem == "mis":
             if lam is None:
                 raise ValueError("MIS needs a penalty grid lambda [S]")
@@ -120,12 +124,19 @@ class CPRASolver:
 
     # -- parameters ---------------------------------------------------------
     def load_params(self, p: Dict[str, object]) -> None:
-        """Copy {"emb", "layers": [{"Ws","Wn"[,"b"]}]} float32 arrays into the flat layout."""
+        """Copy {"emb", "layers": [{"Ws","Wn"[,"b"]}]} float32 arrays into the flat layout
+        (with per-graph weights, Ws / Wn [G, out, in] and b [G, out])."""
         flat = np.zeros(self.n_params, dtype=np.float32)
         emb = np.asarray(p["emb"], dtype=np.float32)
         flat[: emb.size] = emb.ravel()
+        in_dim = self.model_cfg.in_dim
         for k, L in enumerate(p["layers"]):
             ows, own, ob = self.offsets[1 + 3 * k: 4 + 3 * k]
+            d_out = self.cfg.S if k == self.model_cfg.n_layers - 1 else self.cfg.hidden
+            d_in = in_dim if k == 0 else self.cfg.hidden
+            want = (self.G, d_out, d_in) if self.G else (d_out, d_in)
+            if tuple(np.shape(L["Ws"])) != want or tuple(np.shape(L["Wn"])) != want:
+                raise ValueError(f"layer {k}: Ws and Wn must be {want}")
             flat[ows: ows + L["Ws"].size] = np.asarray(L["Ws"], np.float32).ravel()
             flat[own: own + L["Wn"].size] = np.asarray(L["Wn"], np.float32).ravel()
             if ob >= 0:
@@ -143,13 +154,16 @@ class CPRASolver:
         in_dim = self.model_cfg.in_dim
         out = {"emb": a[: N * in_dim].reshape(N, in_dim).copy(), "layers": []}
         d_in = in_dim
+        G = max(self.G, 1)
+        lead = (self.G,) if self.G else ()
         for k in range(self.model_cfg.n_layers):
             d_out = self.cfg.S if k == self.model_cfg.n_layers - 1 else self.cfg.hidden
             ows, own, ob = self.offsets[1 + 3 * k: 4 + 3 * k]
-            L = {"Ws": a[ows: ows + d_out * d_in].reshape(d_out, d_in).copy(),
-                 "Wn": a[own: own + d_out * d_in].reshape(d_out, d_in).copy()}
+            n = G * d_out * d_in
+            L = {"Ws": a[ows: ows + n].reshape(lead + (d_out, d_in)).copy(),
+                 "Wn": a[own: own + n].reshape(lead + (d_out, d_in)).copy()}
             if ob >= 0:
-                L["b"] = a[ob: ob + d_out].copy()
+                L["b"] = a[ob: ob + G * d_out].reshape(lead + (d_out,)).copy()
             out["layers"].append(L)
             d_in = d_out
         return out

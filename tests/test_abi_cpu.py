@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = _lib.lib()
-    assert lib.cpra_abi_version() == 4
+    assert lib.cpra_abi_version() == 5
     for code, name in _lib.STATUS.items():
         assert lib.cpra_status_string(code).decode() == name
 
@@ -138,6 +138,13 @@ def test_model_param_count_and_offsets_host_only():
     assert offs[0] == 0 and offs[1] == 10 * 128 and offs[2] == offs[1] + 128 * 128
     assert offs[3] == -1 and offs[4] == offs[2] + 128 * 128
     assert api.model_param_count(cfg, 10) == 10 * 128 + 2 * (128 * 128 * 2 + 128 * 64)
+    # one network per graph: every layer block repeated G times (Ws, then Wn, then b)
+    G = 7
+    cfg = api.make_model_cfg(api.SAGE, 2, 16, 16, 8, weight_groups=G)
+    offs = api.model_param_offsets(cfg, 50)
+    assert offs[1] == 50 * 16 and offs[2] == offs[1] + G * 16 * 16 and offs[3] == offs[2] + G * 16 * 16
+    assert offs[4] == offs[3] + G * 16 and offs[5] == offs[4] + G * 8 * 16
+    assert api.model_param_count(cfg, 50) == 50 * 16 + G * (2 * 16 * 16 + 16 + 2 * 8 * 16 + 8)
 
 
 def test_host_argument_errors_need_no_gpu():
