@@ -42,25 +42,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(name: str):
-    from workloads import get_preset, init_params
+def build_workload(name: str, per_graph: bool = False):
+    from workloads import get_preset, init_params, init_params_per_graph
     pr = get_preset(name)
     t0 = time.time()
     g = pr.graph()
     log(f"[bench] workload {name}: n={g.n} edges={g.n_edges} graphs={g.n_graphs} "
         f"({time.time() - t0:.1f}s to generate)")
-    params = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=2024)
+    if per_graph:
+        if g.n_graphs < 2:
+            raise SystemExit("--per-graph-weights needs a batch of graphs (C3, C3s)")
+        params = init_params_per_graph(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S,
+                                       g.n_graphs, seed=2024)
+    else:
+        params = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=2024)
     return pr, g, params
 
 
-def make_solver(pr, g, params):
+def make_solver(pr, g, params, per_graph: bool = False):
     from paper_2402_02190_amd import api
     from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
     dg = api.DeviceGraph.from_csr(g)
     cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
                      hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu,
                      gamma_start=pr.gamma_start, gamma_end=pr.gamma_end, T=pr.T, lr=pr.lr,
-                     recompute=pr.recompute)
+                     recompute=pr.recompute, per_graph_weights=per_graph)
     sol = CPRASolver(dg, cfg, pr.lam)
     sol.load_params(params)
     return sol
@@ -113,7 +119,7 @@ def pmc_pass(sol, steps: int):
     log(f"[bench] pmc pass: calibration copy + {steps} steps done")
 
 
-def cpu_baseline(pr, g, params, seconds: float):
+def cpu_baseline(pr, g, params, seconds: float, per_graph: bool = False):
     """The FP64 oracle's training step timed on the host, on a bounded number of steps."""
     from oracle import gnn as ognn
     from oracle import train as otrain
@@ -132,7 +138,10 @@ def cpu_baseline(pr, g, params, seconds: float):
     while True:
         t0 = time.perf_counter()
         gamma = otrain.gamma_at(len(times), pr.T, pr.gamma_start, pr.gamma_end)
-        _, _, _, grads = otrain.loss_and_grads(p64, M, g, cfg, gamma)
+        if per_graph:
+            _, _, _, grads = otrain.loss_and_grads_per_graph(p64, g, cfg, gamma)
+        else:
+            _, _, _, grads = otrain.loss_and_grads(p64, M, g, cfg, gamma)
         opt.step(p64, grads, cfg)
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > seconds or len(times) >= 200:
@@ -234,6 +243,8 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="C2")
+    ap.add_argument("--per-graph-weights", action="store_true",
+                    help="batched workloads: one network per graph instead of one shared network")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -255,8 +266,9 @@ def main():
         print(json.dumps({"sweep": "loss_fwd_bwd and aggregate, near-20-regular random graphs, S=64",
                           "peak_hbm_GBps": PEAK_HBM_GBS, "rows": rows}), flush=True)
         return
+    label = args.workload + ("_pergraph" if args.per_graph_weights else "")
     if args.tuning_file is None and not args.no_autotune:
-        args.tuning_file = default_tuning_file(args.workload)
+        args.tuning_file = default_tuning_file(label)
     if args.gpus != 1:
         log("bench.py measures one GPU: the library runs one process on one GPU (a batch of graphs "
             "would shard at graph boundaries, one share per GPU). Run with --gpus 1.")
@@ -266,8 +278,8 @@ def main():
     import torch
     from paper_2402_02190_amd import api
 
-    pr, g, params = build_workload(args.workload)
-    sol = make_solver(pr, g, params)
+    pr, g, params = build_workload(args.workload, args.per_graph_weights)
+    sol = make_solver(pr, g, params, args.per_graph_weights)
     torch.cuda.synchronize()
     log(f"[bench] params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
 
@@ -321,10 +333,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{pr.name}: {pr.description}", "n_nodes": g.n,
+        "config": {"workload": f"{pr.name}: {pr.description}"
+                               + ("; one network per graph" if args.per_graph_weights else ""),
+                   "n_nodes": g.n,
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
                    "problem": pr.problem, "hip_graph_replay": True,
+                   "per_graph_weights": bool(args.per_graph_weights),
                    "autotuned_gemm": not args.no_autotune,
                    "ms_per_step_events": ms_event},
     }
@@ -346,9 +361,9 @@ def main():
         kernels = {k: {"launches": v[0], "avg_us": v[1] * 1e3 / v[0],
                        "share": v[1] / total} for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
         dom = max(stats, key=lambda k: stats[k][1])
-        result["roofline"] = roofline_entry(dom, stats[dom], pr.name)
+        result["roofline"] = roofline_entry(dom, stats[dom], label)
         if "loss_fwd_bwd" in stats:
-            result["roofline_loss"] = roofline_entry("loss_fwd_bwd", stats["loss_fwd_bwd"], pr.name)
+            result["roofline_loss"] = roofline_entry("loss_fwd_bwd", stats["loss_fwd_bwd"], label)
         result["kernels"] = kernels
         log(f"[bench] dominant kernel {dom}: {json.dumps(result['roofline'])}")
         for k, v in kernels.items():
@@ -364,7 +379,7 @@ def main():
 
     if rank == 0 and not args.no_cpu_baseline:
         log(f"[bench] timing the FP64 oracle for up to {args.cpu_seconds:.0f}s ...")
-        result["cpu_baseline"] = cpu_baseline(pr, g, params, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(pr, g, params, args.cpu_seconds, args.per_graph_weights)
         log(f"[bench] cpu baseline: {result['cpu_baseline']}")
 
     sol.close()

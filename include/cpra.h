@@ -474,7 +474,7 @@ cpra_status cpra_autotune_get(int32_t i, char* key, size_t key_len, int32_t* cfg
                               char* choice, size_t choice_len, double* us, double* heuristic_us);
 /* Insert or replace an entry (e.g. a table saved by an earlier run): shape key
  * as returned by autotune_get, configuration index (0..19) and split count
- * (1..256; reduced to what the call's workspace holds).  CPRA_ERR_PARAM
+ * (1..1024; reduced to what the call's workspace holds).  CPRA_ERR_PARAM
  * outside those ranges. */
 cpra_status cpra_autotune_set(const char* key, int32_t cfg, int32_t splits);
 

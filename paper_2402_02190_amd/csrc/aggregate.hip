@@ -3,10 +3,10 @@
 //
 // Layout: a 64-lane wavefront holds 64/LPR rows; the LPR lanes of one row
 // cover its columns in VEC-float vectors, NC vectors per lane.  Each lane
-// walks its row's neighbour list (the index loads are uniform across the row's
-// lanes) and issues up to four independent row gathers per iteration; every
-// gathered row segment is read as contiguous, coalesced vectors.  Sums run in
-// CSR order, so results are deterministic.
+// walks its row's neighbour list in chunks (the index loads are uniform across
+// the row's lanes) and issues a chunk's row gathers together; every gathered
+// row segment is read as contiguous, coalesced vectors.  Sums run in CSR
+// order, so results are deterministic.
 #include "common.hpp"
 
 namespace cpra {
@@ -104,41 +104,35 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = O::zero();
 
+  // Neighbours in chunks of CH (all index loads, then all row gathers, then
+  // the adds in CSR order); the entries of a last partial chunk past the
+  // row's end are not gathered and add an exact zero instead (the sums never
+  // hold -0, so x + 0 = x), so a row costs two dependent round trips per
+  // chunk and there is no serial tail.
+  constexpr int CH = NC <= 2 ? 8 : 4;
   const int beg = a.row_ptr[row];
   const int end = a.row_ptr[row + 1];
-  int k = beg;
-  for (; k + 4 <= end; k += 4) {
-    const int j0 = a.col_idx[k], j1 = a.col_idx[k + 1], j2 = a.col_idx[k + 2], j3 = a.col_idx[k + 3];
-    float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
-    if constexpr (TRANS) {
-      s0 = a.inv_deg[j0]; s1 = a.inv_deg[j1]; s2 = a.inv_deg[j2]; s3 = a.inv_deg[j3];
-    }
+  for (int k = beg; k < end; k += CH) {
+    const int n_in = min(CH, end - k);
+    int j[CH];
+    float s[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) j[i] = a.col_idx[min(k + i, end - 1)];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) s[i] = TRANS ? a.inv_deg[j[i]] : 1.f;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int u = c * lpr + cl;
       if (u < units) {
-        const V x0 = *reinterpret_cast<const V*>(a.X + (int64_t)j0 * a.ldx + u * VEC);
-        const V x1 = *reinterpret_cast<const V*>(a.X + (int64_t)j1 * a.ldx + u * VEC);
-        const V x2 = *reinterpret_cast<const V*>(a.X + (int64_t)j2 * a.ldx + u * VEC);
-        const V x3 = *reinterpret_cast<const V*>(a.X + (int64_t)j3 * a.ldx + u * VEC);
-        if constexpr (TRANS) {
-          O::axpy(acc[c], s0, x0); O::axpy(acc[c], s1, x1);
-          O::axpy(acc[c], s2, x2); O::axpy(acc[c], s3, x3);
-        } else {
-          O::add(acc[c], x0); O::add(acc[c], x1); O::add(acc[c], x2); O::add(acc[c], x3);
+        V x[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)  // padded entries are not gathered
+          x[i] = i < n_in ? *reinterpret_cast<const V*>(a.X + (int64_t)j[i] * a.ldx + u * VEC)
+                          : O::zero();
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {  // and add an exact zero (no branch between the adds)
+          if constexpr (TRANS) O::axpy(acc[c], s[i], x[i]); else O::add(acc[c], x[i]);
         }
-      }
-    }
-  }
-  for (; k < end; ++k) {
-    const int j = a.col_idx[k];
-    const float s = TRANS ? a.inv_deg[j] : 1.f;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int u = c * lpr + cl;
-      if (u < units) {
-        const V x = *reinterpret_cast<const V*>(a.X + (int64_t)j * a.ldx + u * VEC);
-        if constexpr (TRANS) O::axpy(acc[c], s, x); else O::add(acc[c], x);
       }
     }
   }

@@ -16,6 +16,7 @@
 //
 // Tile shape and split count come from a table filled by the autotuner
 // (timed candidates per problem shape) or, for untuned shapes, a heuristic.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -128,7 +129,7 @@ int max_k_tiles(const GemmProblem* probs, int n, int bk) {
 }
 
 // Split count that brings the launch to ~512 blocks, keeping >= 4 K steps per split.
-constexpr int kMaxSplits = 256;
+constexpr int kMaxSplits = 1024;
 
 int heuristic_splits(const GemmProblem* probs, int n, const Cfg& c) {
   if (probs[0].group_mode == 1) return 1;  // row-grouped products are never split
@@ -145,6 +146,37 @@ Plan heuristic_plan(const GemmProblem* probs, int n, bool can_split) {
   if (tiles_of(probs, n, kCfgs[5]) >= 1024) p.cfg = 5;
   if (can_split) p.splits = heuristic_splits(probs, n, kCfgs[p.cfg]);
   return p;
+}
+
+size_t partial_floats(int splits, const GemmProblem* probs, int n);
+
+// Split counts the tuner tries for a configuration: 1, the powers of two up to
+// half the K steps, and the heuristic's count and its double, within a launch
+// of at most 32768 blocks and 256 MiB of partial tiles.
+constexpr int64_t kMaxTuneBlocks = 32768;
+constexpr size_t kMaxPartialBytes = size_t(256) << 20;
+
+std::vector<int> split_candidates(const GemmProblem* probs, int n, const Cfg& c) {
+  std::vector<int> out = {1};
+  if (probs[0].group_mode == 1) return out;
+  const int64_t tiles = tiles_of(probs, n, c);
+  const int cap = min(kMaxSplits, max(1, max_k_tiles(probs, n, c.bk) / 2));
+  const int h = heuristic_splits(probs, n, c);
+  std::vector<int> cand;
+  for (int s = 2; s <= cap; s *= 2) cand.push_back(s);
+  if (h > 1) {
+    cand.push_back(h);
+    if (2 * h <= kMaxSplits) cand.push_back(2 * h);
+  }
+  std::sort(cand.begin(), cand.end());
+  for (int s : cand) {
+    if (s == out.back()) continue;
+    if (s != h && (tiles * s > kMaxTuneBlocks ||
+                   partial_floats(s, probs, n) * sizeof(float) > kMaxPartialBytes))
+      continue;
+    out.push_back(s);
+  }
+  return out;
 }
 
 size_t partial_floats(int splits, const GemmProblem* probs, int n) {
@@ -297,14 +329,10 @@ cpra_status tune(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws, 
   const bool log_candidates = env != nullptr && env[0] == '1';
   TuneEntry entry{Plan{0, 1}, 1e30, -1.0};
   for (int c = 0; c < kNumCfgs; ++c) {
-    std::vector<int> splits = {1};
-    const int h = heuristic_splits(probs, n, kCfgs[c]);
-    if (ws != nullptr && h > 1) {
-      for (int s : {h / 2, h, 2 * h})
-        if (s > 1 && s <= kMaxSplits && partial_floats(s, probs, n) * sizeof(float) <= ws_bytes &&
-            s != splits.back())
-          splits.push_back(s);
-    }
+    std::vector<int> splits;
+    for (int s : split_candidates(probs, n, kCfgs[c]))
+      if (s == 1 || (ws != nullptr && partial_floats(s, probs, n) * sizeof(float) <= ws_bytes))
+        splits.push_back(s);
     for (int s : splits) {
       Plan pl{c, s};
       CPRA_CHECK(run_plan(a_t, b_t, probs, n, pl, ws, stream));  // warm-up
@@ -341,13 +369,11 @@ cpra_status tune(bool a_t, bool b_t, const GemmProblem* probs, int n, void* ws, 
 size_t gemm_batch_workspace_bytes(bool a_t, bool b_t, const GemmProblem* probs, int n) {
   (void)a_t;
   (void)b_t;
-  // Room for any candidate the tuner may pick: twice the heuristic split of any config.
+  // Room for any candidate the tuner may pick.
   size_t best = 0;
-  for (int c = 0; c < kNumCfgs; ++c) {
-    const int h = heuristic_splits(probs, n, kCfgs[c]);
-    const int s = h > 1 ? min(kMaxSplits, 2 * h) : 1;
-    if (s > 1) best = std::max(best, partial_floats(s, probs, n) * sizeof(float));
-  }
+  for (int c = 0; c < kNumCfgs; ++c)
+    for (int s : split_candidates(probs, n, kCfgs[c]))
+      if (s > 1) best = std::max(best, partial_floats(s, probs, n) * sizeof(float));
   return best;
 }
 

@@ -107,6 +107,9 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
       ap[c] = 0.0f;
     }
     if (active) {
+      // Neighbours in full chunks of 4 (index and weight loads, then the four
+      // gathers, then the adds in CSR order), and the remaining 1-3 as one
+      // predicated chunk, so that the tail costs one round trip, not one each.
       const int beg = a.row_ptr[row], end = a.row_ptr[row + 1];
       int k = beg;
       for (; k + 4 <= end; k += 4) {
@@ -128,13 +131,30 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
           }
         }
       }
-      for (; k < end; ++k) {
-        const int j = a.col_idx[k];
-        const float w = a.weight ? a.weight[k] : 1.f;
+      if (k < end) {  // 1-3 left
+        // entries past the end re-read the row's last neighbour (and add 0)
+        const int n_left = end - k;
+        const int j0 = a.col_idx[k];
+        const int j1 = a.col_idx[min(k + 1, end - 1)];
+        const int j2 = a.col_idx[min(k + 2, end - 1)];
+        float w0 = 1.f, w1 = 1.f, w2 = 1.f;
+        if (a.weight) {
+          w0 = a.weight[k];
+          w1 = a.weight[min(k + 1, end - 1)];
+          w2 = a.weight[min(k + 2, end - 1)];
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const int s = c * lpr + cl;
-          if (s < S) ap[c] += w * a.P[(int64_t)j * a.ldp + s];
+          if (s < S) {
+            const float p0 = a.P[(int64_t)j0 * a.ldp + s];
+            const float p1 = a.P[(int64_t)j1 * a.ldp + s];
+            const float p2 = a.P[(int64_t)j2 * a.ldp + s];
+            // padded entries add an exact zero (weight 0 by a select, no branch)
+            ap[c] += w0 * p0;
+            ap[c] += (n_left > 1 ? w1 : 0.f) * p1;
+            ap[c] += (n_left > 2 ? w2 : 0.f) * p2;
+          }
         }
       }
     }
