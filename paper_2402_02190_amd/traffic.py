@@ -30,7 +30,8 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 CALIBRATION_BYTES = 1 << 30
 
 # family (as the library's profiler names it) -> source files of its kernel
-_SOURCES = {"gemm": ("gemm.hip", "common.hpp"), "aggregate": ("aggregate.hip", "common.hpp"),
+_SOURCES = {"gemm": ("gemm.hip", "gemm_kernel.hpp", "gemm_grouped.hip", "common.hpp"),
+            "aggregate": ("aggregate.hip", "common.hpp"),
             "loss_fwd_bwd": ("loss.hip", "common.hpp"), "adam": ("adam.hip", "common.hpp")}
 
 
@@ -51,12 +52,17 @@ def source_hash(family: str) -> str:
 
 def kernel_pattern(family: str) -> re.Pattern:
     """Regex on rocprofv3's demangled kernel name for a profiler family."""
-    m = re.fullmatch(r"gemm_([nt])([nt])_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)", family)
+    # gemm_<layout>[_byrow|_byk]_<BM>x<BN>x<BK>_w<WM>x<WN>[_p2] -> k_gemm<BM, BN, BK, WM, WN,
+    # A_T, B_T, PF, GM> (PF: prefetch distance, GM: group mode 0 / 1 by rows / 2 by K)
+    m = re.fullmatch(r"gemm_([nt])([nt])(_byrow|_byk)?_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)(_p2)?", family)
     if m:
-        at, bt, bm, bn, bk, wm, wn = m.groups()
+        at, bt, grp, bm, bn, bk, wm, wn, p2 = m.groups()
+        gm = {None: 0, "_byrow": 1, "_byk": 2}[grp]
         args = f"{bm}, {bn}, {bk}, {wm}, {wn}, {'true' if at == 't' else 'false'}, " \
-               f"{'true' if bt == 't' else 'false'}"
+               f"{'true' if bt == 't' else 'false'}, {2 if p2 else 1}, {gm}"
         return re.compile(re.escape(f"k_gemm<{args}>"))
+    if family == "gemm_splitk_reduce":
+        return re.compile(r"k_gemm_splitk_reduce")
     if family == "aggregate":
         return re.compile(r"k_aggregate<\d+, \d+, false>")
     if family == "aggregate_transposed":

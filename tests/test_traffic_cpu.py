@@ -12,8 +12,15 @@ from paper_2402_02190_amd import traffic as TR
 
 def test_kernel_pattern_maps_profiler_families_to_trace_names():
     p = TR.kernel_pattern("gemm_tn_64x128x32_w2x2")
-    assert p.search("void cpra::(anonymous namespace)::k_gemm<64, 128, 32, 2, 2, true, false>(x)")
-    assert not p.search("void cpra::(anonymous namespace)::k_gemm<64, 128, 32, 2, 2, false, false>(x)")
+    assert p.search("void cpra::gemmk::k_gemm<64, 128, 32, 2, 2, true, false, 1, 0>(x)")
+    assert not p.search("void cpra::gemmk::k_gemm<64, 128, 32, 2, 2, false, false, 1, 0>(x)")
+    assert not p.search("void cpra::gemmk::k_gemm<64, 128, 32, 2, 2, true, false, 2, 0>(x)")
+    assert TR.kernel_pattern("gemm_nt_byrow_64x32x16_w1x1_p2").search(
+        "void cpra::gemmk::k_gemm<64, 32, 16, 1, 1, false, true, 2, 1>(x)")
+    assert TR.kernel_pattern("gemm_tn_byk_64x64x32_w2x2_p2").search(
+        "void cpra::gemmk::k_gemm<64, 64, 32, 2, 2, true, false, 2, 2>(x)")
+    assert not TR.kernel_pattern("gemm_tn_64x64x32_w2x2_p2").search(
+        "void cpra::gemmk::k_gemm<64, 64, 32, 2, 2, true, false, 2, 2>(x)")
     assert TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, false>(a)")
     assert not TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, true>(a)")
     assert TR.kernel_pattern("loss_fwd_bwd").search("cpra::k_loss<2>(args)")
@@ -32,7 +39,7 @@ def _write_counters(d, counter, rows):
 
 def test_measure_scales_each_counter_by_the_calibration_copy(tmp_path, monkeypatch):
     copy = 1 << 20
-    k = "void cpra::(anonymous namespace)::k_gemm<64, 64, 16, 2, 2, false, false>(L)"
+    k = "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 1, 0>(L)"
     # FETCH reads half the true bytes, WRITE exactly them (factors 0.5 and 1.0)
     _write_counters(tmp_path / "F", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", copy / 1024 / 2),
                                                     (k, 100.0), (k, 300.0), ("other", 5.0)])
