@@ -87,6 +87,80 @@ def test_full_size_step_teacher_forced(preset):
     sol.close()
 
 
+def test_full_size_per_graph_c3_sampled_graphs():
+    """C3 with one network per graph (256 graphs, 710,241 nodes) in bench.py's launch
+    configuration (the committed per-graph GEMM plans, a captured and replayed step):
+    the graphs are independent problems, so sampled graphs -- the smallest, the largest
+    and three more -- are each checked against the oracle run on that graph alone."""
+    import json
+    import os
+    from paper_2402_02190_amd import api
+    from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver, gamma_schedule
+    from workloads import init_params_per_graph
+    pr = get_preset("C3")
+    g = pr.graph()
+    G = g.n_graphs
+    say(f"full-size C3 per graph: n={g.n} graphs={G}")
+    table = os.path.join(os.path.dirname(api.__file__), "tuning", "c3_pergraph_mi355x.json")
+    with open(table) as f:
+        for e in json.load(f):
+            api.autotune_set(e["key"], e["cfg"], e["splits"])
+    try:
+        dg = api.DeviceGraph.from_csr(g)
+        cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
+                         hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu,
+                         gamma_start=pr.gamma_start, gamma_end=pr.gamma_end, T=pr.T, lr=pr.lr,
+                         per_graph_weights=True)
+        sol = CPRASolver(dg, cfg, pr.lam)
+        sol.load_params(init_params_per_graph(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, G,
+                                              seed=7))
+        sol.step()
+        torch.cuda.synchronize()
+        t = sol.t
+        p_before = ognn.to_f64(sol.unpack(sol.params))
+        sol.capture()
+        sol.replay(1)
+        torch.cuda.synchronize()
+        gamma = gamma_schedule(t, pr.T, pr.gamma_start, pr.gamma_end)
+        gp = np.asarray(g.graph_ptr, dtype=np.int64)
+        sizes = np.diff(gp)
+        picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, G // 2, G - 1})
+        Z = sol.Z.cpu().numpy()
+        dZ = sol.dZ.cpu().numpy()
+        T = sol.terms_host()
+        gg = sol.unpack(sol.grads)
+        active = sol.relu_active()
+        ocfg = otrain.StepConfig(problem=pr.problem, lam=None, alpha=pr.alpha, nu=pr.nu, lr=pr.lr)
+        for b in picks:
+            lo, hi = int(gp[b]), int(gp[b + 1])
+            sub = oobj._slice_graph(g, lo, hi)
+            M = ognn.mean_aggregation_matrix(sub.row_ptr, sub.col_idx)
+            act_b = [a[lo:hi] for a in active]
+            Zo, terms_o, dZo, go, cache = otrain.loss_and_grads(
+                otrain.graph_params(p_before, b, lo, hi), M, sub, ocfg, gamma, relu_active=act_b,
+                return_cache=True)
+            say(f"  graph {b}: {hi - lo} nodes")
+            for k, act in enumerate(act_b):  # taken ReLU decisions differ only at Y ~ 0
+                Y = cache[k]["Y"]
+                flips = act != (Y > 0)
+                assert np.all(np.abs(Y[flips]) <= 1e-5 * np.sqrt(np.mean(Y * Y)))
+            assert_close_array(Z[lo:hi], Zo, what=f"graph {b} Z")
+            assert_close_array(dZ[lo:hi], dZo, what=f"graph {b} dZ")
+            assert_close_array(gg["emb"][lo:hi], go["emb"], what=f"graph {b} d emb")
+            for k in range(pr.n_layers):
+                for key in go["layers"][k]:
+                    assert_close_array(gg["layers"][k][key][b], go["layers"][k][key],
+                                       what=f"graph {b} d{key}{k}")
+            to = terms_o[0]
+            for s in range(pr.S):
+                assert_close_scalar(T[b, s], to["head"][s], abs(to["head"][s]) + 1.0, what="l_s")
+            assert_close_scalar(T[b, pr.S], to["entropy"], to["entropy"], what="S(P)")
+            assert_close_scalar(T[b, pr.S + 1], to["psi"], abs(to["psi"]), what="Psi")
+        sol.close()
+    finally:
+        api.autotune_reset()
+
+
 def test_c4_backward_on_1k_subgraph_matches_finite_differences():
     """Hand-written backward (GPU) vs the oracle's analytic gradient vs FP64 central
     differences, on the subgraph induced by a 1,000-node BFS ball of the
