@@ -405,12 +405,9 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs_in, int n, v
       probs = local;
     }
   }
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     if (probs[i].bias_grad && probs[i].bias)
       CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad and bias are exclusive");
-    if (probs[i].bias_grad && !a_t)
-      CPRA_FAIL(CPRA_ERR_PARAM, "gemm: bias_grad needs A stored [K, M]");
-  }
   int live = 0;
   for (int i = 0; i < n; ++i)
     if (probs[i].M > 0 && n_eff_of(probs[i]) > 0) ++live;

@@ -73,22 +73,11 @@ struct LaunchArgs {
   int row_counts[3];
 };
 
-// One operand tile in LDS, loaded by NT threads as float4 vectors.
-//  * K-contiguous operands (KCONTIG) keep their memory layout: [R][BK], row r's
-//    16-byte chunk c stored at chunk position c ^ swz(r), so that both the
-//    float4 stores and the 16-byte MFMA operand reads of 8 consecutive rows
-//    cover all 32 banks (conflict-free) -- one ds_write_b128 per loaded
-//    vector and one ds_read_b128 per 4 k values;
-//  * the other operands are stored [BK][R + 4] (MN contiguous), read 4 bytes
-//    per lane.
+// One operand tile [BK][R] in LDS, loaded by NT threads as float4 vectors.
 template <int R, int BK, int NT, bool KCONTIG>
 struct Tile {
-  static_assert(BK % 8 == 0 && BK <= 32, "BK: 8, 16 or 32");
-  static constexpr int PAD = KCONTIG ? 0 : 4;
-  static constexpr int LD = KCONTIG ? BK : R + PAD;  // LDS row stride (floats)
-  static constexpr int SIZE = KCONTIG ? R * BK : BK * LD;
-  static constexpr int CPR = BK / 4;     // 16-byte chunks per row (KCONTIG)
-  static constexpr int RPB = 8 / CPR;    // rows per 128-byte bank row (KCONTIG)
+  static constexpr int PAD = KCONTIG ? 1 : 4;
+  static constexpr int LD = R + PAD;  // LDS row stride (floats)
   static constexpr int NV = R * BK / 4 / NT;
   static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
   float4 reg[NV];
@@ -139,17 +128,17 @@ struct Tile {
     }
   }
 
-  // chunk position of chunk c of row r (KCONTIG layout)
-  __device__ static inline int pos(int r, int c) { return c ^ ((r / RPB) % CPR); }
-
   __device__ inline void store(float* __restrict__ Xs, int tid) const {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int idx = tid + v * NT;
       if constexpr (KCONTIG) {
-        const int r = idx / CPR;
-        const int c = idx % CPR;
-        *reinterpret_cast<float4*>(Xs + r * BK + pos(r, c) * 4) = reg[v];
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        Xs[(kq + 0) * LD + r] = reg[v].x;
+        Xs[(kq + 1) * LD + r] = reg[v].y;
+        Xs[(kq + 2) * LD + r] = reg[v].z;
+        Xs[(kq + 3) * LD + r] = reg[v].w;
       } else {
         const int k = idx / (R / 4);
         const int rq = (idx % (R / 4)) * 4;
@@ -189,8 +178,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   static_assert(TM >= 1 && TN >= 1 && TM * 32 * WM == BM && TN * 32 * WN == BN, "bad tiling");
   using TA = Tile<BM, BK, NT, !A_T>;
   using TB = Tile<BN, BK, NT, B_T>;
-  __shared__ __attribute__((aligned(16))) float As[2][TA::SIZE];
-  __shared__ __attribute__((aligned(16))) float Bs[2][TB::SIZE];
+  __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
 
   // XCD-aware order: the hardware deals consecutive block ids round-robin to
   // the 8 XCDs, each with its own L2.
@@ -287,79 +276,34 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   // outside the matrix is already in the tile).
   constexpr int BG = NT / BM > 0 ? NT / BM : 1;  // threads per row
   static_assert(BK % BG == 0, "bias slice");
-  const bool do_bias = A_T && bgrad_g != nullptr && tn_idx == 0;  // A stored [K, M] only
+  const bool do_bias = bgrad_g != nullptr && tn_idx == 0;
   const int b_row = tid % BM, b_grp = tid / BM;
   float bsum = 0.f;
 
-  // Operand reads of a K step.  The contraction order within each group of 8
-  // k values is permuted: MFMA 4j + i takes k = 8j + i from the lanes of half 0
-  // and k = 8j + 4 + i from the lanes of half 1 (both operands alike), so that
-  // a lane's four k values of a group are one 16-byte chunk of a KCONTIG tile.
-  auto read_a = [&](const float* as, int j, int i, float (&f)[4]) {
-    const int row = (wm * TM + i) * 32 + l32;
-    if constexpr (!A_T) {
-      const float4 v = *reinterpret_cast<const float4*>(as + row * BK + TA::pos(row, 2 * j + half) * 4);
-      f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) f[q] = as[(8 * j + 4 * half + q) * TA::LD + row];
-    }
-  };
-  auto read_b = [&](const float* bs, int j, int i, float (&f)[4]) {
-    const int col = (wn * TN + i) * 32 + l32;
-    if constexpr (B_T) {
-      const float4 v = *reinterpret_cast<const float4*>(bs + col * BK + TB::pos(col, 2 * j + half) * 4);
-      f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) f[q] = bs[(8 * j + 4 * half + q) * TB::LD + col];
-    }
-  };
   // multiply the tile staged in LDS buffer `cur` (and add its A rows for the bias)
   auto compute = [&](int cur) {
     const float* as = As[cur];
     const float* bs = Bs[cur];
-    if constexpr (A_T) {  // bias gradients are only formed with A stored [K, M]
-      if (do_bias && b_grp < BG) {
+    if (do_bias && b_grp < BG) {
 #pragma unroll
-        for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
-      }
+      for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
     }
-    // fragments of group j + 1 are read before the MFMAs of group j
-    float af[2][TM][4], bf[2][TN][4];
+    float af[BK / 2][TM], bf[BK / 2][TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) read_a(as, 0, i, af[0][i]);
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kr = 2 * kk + half;
 #pragma unroll
-    for (int i = 0; i < TN; ++i) read_b(bs, 0, i, bf[0][i]);
+      for (int i = 0; i < TM; ++i) af[kk][i] = as[kr * TA::LD + (wm * TM + i) * 32 + l32];
 #pragma unroll
-    for (int j = 0; j < BK / 8; ++j) {
-      const int cb = j & 1;
-      if (j + 1 < BK / 8) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i) read_a(as, j + 1, i, af[cb ^ 1][i]);
-#pragma unroll
-        for (int i = 0; i < TN; ++i) read_b(bs, j + 1, i, bf[cb ^ 1][i]);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int jj = 0; jj < TN; ++jj)
-            acc[i][jj] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[cb][i][q], bf[cb][jj][q], acc[i][jj], 0, 0, 0);
+      for (int j = 0; j < TN; ++j) bf[kk][j] = bs[kr * TB::LD + (wn * TN + j) * 32 + l32];
     }
-    // Pin that order (the scheduler would otherwise reuse the fragment
-    // registers and wait on every read): the reads of group 0, then per group
-    // the reads of the next group ahead of this group's MFMAs.  A fragment is
-    // one 16-byte read (KCONTIG) or two paired 4-byte reads.  Masks: 0x100 LDS
-    // reads, 0x008 MFMA.
-    constexpr int RD = TM * (A_T ? 2 : 1) + TN * (B_T ? 1 : 2);
-    __builtin_amdgcn_sched_group_barrier(0x100, RD, 0);
 #pragma unroll
-    for (int j = 0; j < BK / 8; ++j) {
-      if (j + 1 < BK / 8) __builtin_amdgcn_sched_group_barrier(0x100, RD, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 4 * TM * TN, 0);
-    }
+    for (int kk = 0; kk < BK / 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][i], bf[kk][j], acc[i][j], 0, 0, 0);
   };
 
   if constexpr (PF == 1) {
