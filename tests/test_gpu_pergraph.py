@@ -255,3 +255,20 @@ def test_per_graph_rejects_a_mismatched_group_count():
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     with pytest.raises(CpraError):
         a.model_forward(dg, cfg, params, Z, ws)
+
+
+def test_shared_vs_per_graph_comparison_runs():
+    """The quality comparison (pergraph.py) on a small batch: both arms train, and each
+    graph's best value is a valid cut of that graph (between 0 and its edge count)."""
+    from paper_2402_02190_amd import pergraph
+    from workloads.presets import Preset
+    g = ragged_batch()
+    pr = Preset("small", "maxcut", "gcn", 2, 16, 8, None, -2.0, 0.1, 40, nu=0.1)
+    a = api()
+    dg = a.DeviceGraph.from_csr(g)
+    for per_graph in (False, True):
+        best, seconds = pergraph.train_arm(pr, g, dg, per_graph, seed=1, T=40)
+        assert best.shape == (g.n_graphs,) and seconds > 0
+        for b, (lo, hi) in enumerate(graph_rows(g)):
+            m = int(g.row_ptr[hi] - g.row_ptr[lo]) // 2
+            assert 0 <= best[b] <= m
