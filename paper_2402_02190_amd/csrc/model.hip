@@ -27,6 +27,7 @@
 // linear-first order the bias moves into the self-weight GEMM's epilogue
 // (it is graph g's bias for graph g's rows).
 #include <algorithm>
+#include <functional>
 
 #include "common.hpp"
 
@@ -273,10 +274,13 @@ struct PendingReads {
 };
 
 // rows_ready: the row-tile maps of per-graph weights are in ws already (built
-// by the forward of the same step).
+// by the forward of the same step).  side_task (optional, with a side stream):
+// work enqueued on the side stream right after the first fork -- the
+// training step's loss-term reduction, so that it needs no fork of its own.
 cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params, const float* dZ,
                           int64_t lddz, float* grads, void* ws, hipStream_t st,
-                          SideStream* side, bool rows_ready) {
+                          SideStream* side, bool rows_ready,
+                          const std::function<cpra_status(hipStream_t)>* side_task = nullptr) {
   const int N = g->n_nodes;
   GroupRows rows{};
   if (p.G > 1) {
@@ -289,6 +293,13 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
   }
   const hipStream_t wst = side ? side->stream : st;  // stream of the weight gradients
   PendingReads pending;
+  auto forked = [&]() -> cpra_status {  // after each fork: the pending side task, once
+    if (side_task && *side_task) {
+      CPRA_CHECK((*side_task)(side->stream));
+      side_task = nullptr;
+    }
+    return CPRA_OK;
+  };
   auto before_write = [&](const void* buf) -> cpra_status {
     if (side && pending.has(buf)) {
       CPRA_CHECK(join_from(side, st));
@@ -319,6 +330,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
       if (side) {
         CPRA_CHECK(fork_to(side, st));
+        CPRA_CHECK(forked());
         pending.add(dY);
         pending.add(T);
       }
@@ -351,6 +363,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
     } else {
       if (side) {
         CPRA_CHECK(fork_to(side, st));
+        CPRA_CHECK(forked());
         pending.add(dY);
       }
       const float* AX;
@@ -532,14 +545,22 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
                           ws_bytes - model_bytes, st, terms != nullptr));
   // The step counter advances (t -> t + 1) after the loss has read t and before
   // Adam reads t + 1: done by one thread of the loss-term reduction, or by a
-  // one-thread kernel when no terms are wanted.
-  if (terms) {  // the per-graph loss terms are off the critical path
-    if (side) CPRA_CHECK(fork_to(side, st));
-    CPRA_CHECK(loss_terms_reduce(g, &lc, terms, loss_ws, side ? side->stream : st, step_counter));
+  // one-thread kernel when no terms are wanted.  With a side stream the
+  // per-graph loss terms are reduced there, enqueued by the backward right
+  // after its first fork (off the critical path, no fork of their own); Adam
+  // runs after the join.  (Adam cannot be split across the streams: the side
+  // stream's first-layer weight gradient reads the embedding, and the main
+  // stream's last products read the layer weights.)
+  std::function<cpra_status(hipStream_t)> terms_task = [&](hipStream_t s2) {
+    return loss_terms_reduce(g, &lc, terms, loss_ws, s2, step_counter);
+  };
+  if (terms) {
+    if (!side) CPRA_CHECK(terms_task(st));
   } else if (step_counter) {
     CPRA_CHECK(increment_counter(step_counter, st));
   }
-  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side, true));
+  CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side, true,
+                           side && terms ? &terms_task : nullptr));
   if (side) CPRA_CHECK(join_from(side, st));
   // only the trainable tail [first trained layer, end) when the encoder is frozen
   const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : 0;
