@@ -330,3 +330,48 @@ def test_frozen_encoder_step(case):
         assert torch.equal(getattr(sols[0], attr), getattr(sols[1], attr)), attr
     for s in sols:
         s.close()
+
+
+@pytest.mark.parametrize("t_at", [10, 1000, 1999])
+def test_train_step_teacher_forced_late_steps(t_at):
+    """Step parity later in the schedule (t = 10, T/2, T-1 of T = 2000): the GPU runs
+    t steps from the captured graph, then one more eager step whose loss terms and
+    gradients the oracle recomputes in FP64 from the GPU's parameters at t (ReLU
+    decisions taken from the GPU's forward).  Late steps have gamma > 0 and
+    saturated P, where 1 - P must not be formed by cancellation."""
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.solver import gamma_schedule
+    pr = get_preset("C1")
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=32, S=10, T=pr.T,
+                     gamma_start=pr.gamma_start, gamma_end=pr.gamma_end, lr=pr.lr)
+    sol = CPRASolver(dg, cfg, pr.lam)
+    sol.load_params(init_params("gcn", g.n, 2, 32, 10, seed=13))
+    sol.run(t_at, use_graph=True)
+    torch.cuda.synchronize()
+    t = int(sol.step_counter.item())
+    assert t == t_at
+    p_before = sol.unpack(sol.params)
+    sol.step()
+    torch.cuda.synchronize()
+    gamma = gamma_schedule(t, cfg.T, cfg.gamma_start, cfg.gamma_end)
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    ocfg = otrain.StepConfig(problem="mis", lam=pr.lam.astype(np.float64), lr=pr.lr)
+    Zo, terms_o, dZo, go = otrain.loss_and_grads(ognn.to_f64(p_before), M, g, ocfg, gamma,
+                                                 relu_active=sol.relu_active())
+    say(f"t={t}: gamma={gamma:.4f}, max |Z|={np.abs(Zo).max():.1f}")
+    assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what=f"[{t}] Z")
+    assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what=f"[{t}] dZ")
+    gg = sol.unpack(sol.grads)
+    assert_close_array(gg["emb"], go["emb"], what=f"[{t}] d emb")
+    for k in range(2):
+        for key in go["layers"][k]:
+            assert_close_array(gg["layers"][k][key], go["layers"][k][key], what=f"[{t}] d{key}{k}")
+    T_gpu = sol.terms.cpu().numpy()
+    to = terms_o[0]
+    for s in range(cfg.S):
+        assert_close_scalar(T_gpu[0, s], to["head"][s], abs(to["head"][s]) + 1.0, what="l_s")
+    assert_close_scalar(T_gpu[0, cfg.S], to["entropy"], to["entropy"] + 1e-9, what="S(P)")
+    assert int(sol.step_counter.item()) == t + 1
+    sol.close()

@@ -254,3 +254,28 @@ def test_cpra_with_z_offset_matches_oracle(S, hidden):
     torch.cuda.synchronize()
     Zplain, _ = ognn.forward(ognn.to_f64(p), M)
     assert_close_array(sol2.Z.cpu().numpy(), Zplain, what="Z without offset")
+
+
+def test_zero_offset_reproduces_the_plain_method_bit_for_bit():
+    """A warm start of all zeros changes nothing: 20 training steps with z_offset = 0
+    give the same parameters and loss terms, bit for bit, as without an offset."""
+    api = api_mod()
+    from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
+    for kind, S, hidden in (("gcn", 10, 32), ("sage", 40, 16)):  # output layer linear-first / aggregate-first
+        g = random_regular_graph(300, 3, 9)
+        dg = api.DeviceGraph.from_csr(g)
+        lam = np.linspace(0.5, 5, S).astype(np.float32)
+        cfg = CPRAConfig(problem="mis", layer_kind=kind, n_layers=2, hidden=hidden, S=S)
+        p = init_params(kind, g.n, 2, hidden, S, seed=6)
+        zero = torch.zeros((g.n, S), dtype=torch.float32, device="cuda")
+        a = CPRASolver(dg, cfg, lam, z_offset=zero)
+        b = CPRASolver(dg, cfg, lam)
+        a.load_params(p)
+        b.load_params(p)
+        a.run(20, use_graph=True)
+        b.run(20, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a.params, b.params), kind
+        assert torch.equal(a.terms, b.terms), kind
+        a.close()
+        b.close()
