@@ -119,3 +119,13 @@ def test_star_triangles_and_features():
         fo, to = W.node_features(g, rand, 16)
         assert np.array_equal(tri.cpu().numpy()[: g.n], to)
         assert np.array_equal(feat.cpu().numpy()[: g.n].view(np.uint16), W.bf16_bits(fo))
+
+
+def test_single_node_graph_step_matches_oracle():
+    _step_vs_oracle(edgeless(1), kind="sage", what="N=1")
+
+
+def test_one_head_step_matches_oracle():
+    _step_vs_oracle(random_regular_graph(80, 3, 7), kind="gcn", H=16, S=1, what="S=1")
+    _step_vs_oracle(random_regular_graph(80, 3, 7), kind="sage", H=16, S=1, problem="maxcut",
+                    what="S=1 maxcut")
