@@ -192,7 +192,7 @@ def test_autograd_function_matches_backward():
     M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
     ocfg = otrain.StepConfig(problem="mis", lam=lam.astype(np.float64))
     Zo, terms, dZo, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, -0.5)
-    assert abs(float(R) - terms[0]["total"]) <= 1e-5 * (np.abs(terms[0]["head"]).sum() + 0.5 * terms[0]["entropy"])
+    assert abs(float(R.detach()) - terms[0]["total"]) <= 1e-5 * (np.abs(terms[0]["head"]).sum() + 0.5 * terms[0]["entropy"])
     gg = sol.unpack(params.grad)
     assert_close_array(gg["emb"], go["emb"], what="autograd d emb")
     assert_close_array(gg["layers"][1]["Wn"], go["layers"][1]["Wn"], what="autograd dWn1")
