@@ -281,6 +281,7 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
                      hipStream_t stream) {
   LaunchArgs args;
   fill_args(probs, n, pl.splits, ws, &args);
+  const int cfg = pf2_ok(args, a_t, b_t) ? pl.cfg : kPf1Twin[pl.cfg];
   double flops = 0, red_bytes = 0;
   for (int i = 0; i < n; ++i) {
     const double mn = (double)args.p[i].M * args.p[i].N;
@@ -292,14 +293,14 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
   static const char* gmode[3] = {"", "_byrow", "_byk"};
   const int mode = probs[0].group_mode;
   char pname[64];
-  snprintf(pname, sizeof(pname), "gemm_%s%s_%s", layout[a_t][b_t], gmode[mode], kCfgNames[pl.cfg]);
+  snprintf(pname, sizeof(pname), "gemm_%s%s_%s", layout[a_t][b_t], gmode[mode], kCfgNames[cfg]);
   {
     ProfScope ps(pname, stream, flops, 0.0);
-    if (mode) launch_grouped(mode, a_t, b_t, pl.cfg, args, stream);
-    else if (!a_t && b_t) launch_any<false, true, 0>(pl.cfg, args, stream);
-    else if (!a_t && !b_t) launch_any<false, false, 0>(pl.cfg, args, stream);
-    else if (a_t && !b_t) launch_any<true, false, 0>(pl.cfg, args, stream);
-    else launch_any<true, true, 0>(pl.cfg, args, stream);
+    if (mode) launch_grouped(mode, a_t, b_t, cfg, args, stream);
+    else if (!a_t && b_t) launch_any<false, true, 0>(cfg, args, stream);
+    else if (!a_t && !b_t) launch_any<false, false, 0>(cfg, args, stream);
+    else if (a_t && !b_t) launch_any<true, false, 0>(cfg, args, stream);
+    else launch_any<true, true, 0>(cfg, args, stream);
   }
   CPRA_CHECK_LAUNCH("gemm");
   if (pl.splits > 1) {

@@ -128,6 +128,61 @@ struct Tile {
     }
   }
 
+  // Branch-free load for the two-deep prefetch: every access is one float4 at
+  // a clamped, in-bounds address.  Rows or columns past mn_lim only feed
+  // outputs that are never stored; vectors past k_lim are flagged in `ok` and
+  // zeroed by store_masked, so no loaded value is consumed before the LDS
+  // store that has to wait for it anyway.  Requires float4-aligned operands,
+  // mn_lim >= 4 when MN is the contiguous axis, and k_lim a multiple of 4
+  // (relative to k0) when K is the contiguous axis (see pf2_ok).
+  unsigned ok;
+  __device__ inline void load_clamped(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim,
+                                      int k0, int k_lim, int tid) {
+    ok = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      if constexpr (KCONTIG) {
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        const int gm = min(mn0 + r, mn_lim - 1);
+        const bool val = k0 + kq < k_lim;
+        const int gk = val ? k0 + kq : k_lim - 4;
+        reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gm * ld + gk);
+        ok |= (unsigned)val << v;
+      } else {
+        const int k = idx / (R / 4);
+        const int rq = (idx % (R / 4)) * 4;
+        const bool val = k0 + k < k_lim;
+        const int gk = val ? k0 + k : k_lim - 1;
+        const int gm = min(mn0 + rq, mn_lim - 4);
+        reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gk * ld + gm);
+        ok |= (unsigned)val << v;
+      }
+    }
+  }
+
+  __device__ inline void store_masked(float* __restrict__ Xs, int tid) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = tid + v * NT;
+      const bool val = (ok >> v) & 1u;
+      const float4 x = val ? reg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (KCONTIG) {
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        Xs[(kq + 0) * LD + r] = x.x;
+        Xs[(kq + 1) * LD + r] = x.y;
+        Xs[(kq + 2) * LD + r] = x.z;
+        Xs[(kq + 3) * LD + r] = x.w;
+      } else {
+        const int k = idx / (R / 4);
+        const int rq = (idx % (R / 4)) * 4;
+        *reinterpret_cast<float4*>(Xs + k * LD + rq) = x;
+      }
+    }
+  }
+
   __device__ inline void store(float* __restrict__ Xs, int tid) const {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -267,8 +322,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
     const int pc = kt < nt0 ? 0 : 1;
     const int k0 = kb + (kt - (pc ? nt0 : 0)) * BK;
     const int kl = kb + (pc ? kn1 : kn0);
-    ta.load(P.A[pc], P.lda[pc], m0, m_lim, k0, kl, pc ? vA1 : vA0, tid);
-    tb.load(P.B[pc] + b_off, P.ldb[pc], n0, P.N, k0, kl, pc ? vB1 : vB0, tid);
+    if constexpr (PF == 2) {
+      ta.load_clamped(P.A[pc], P.lda[pc], m0, m_lim, k0, kl, tid);
+      tb.load_clamped(P.B[pc] + b_off, P.ldb[pc], n0, P.N, k0, kl, tid);
+    } else {
+      ta.load(P.A[pc], P.lda[pc], m0, m_lim, k0, kl, pc ? vA1 : vA0, tid);
+      tb.load(P.B[pc] + b_off, P.ldb[pc], n0, P.N, k0, kl, pc ? vB1 : vB0, tid);
+    }
   };
   // Bias gradient (row sums of op(A) over this block's K range): the blocks of
   // the first column tile add up the staged A tile with plain VALU adds, thread
@@ -330,27 +390,30 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
     // Two register sets; the loop is unrolled by two so that every set is
     // named statically.  In the body for tile kt: LDS[cur] holds tile kt, set
     // `nxt` holds tile kt + 1 (stored to LDS[cur ^ 1] at the end), and set
-    // `fre` (whose tile kt is already in LDS) receives tile kt + 2.
+    // `fre` (whose tile kt is already in LDS) receives tile kt + 2.  The loads
+    // are unconditional (past the last tile they re-read it, unused) and
+    // branch-free, so the compiler can wait for set `nxt` alone while the
+    // loads of set `fre` stay in flight.
     TA ta0, ta1;
     TB tb0, tb1;
     auto body = [&](int kt, int cur, TA& fre_a, TB& fre_b, TA& nxt_a, TB& nxt_b) {
-      if (kt + 2 < kt_end) load_into(fre_a, fre_b, kt + 2);
-      compute(cur);
+      load_into(fre_a, fre_b, min(kt + 2, kt_end - 1));
+      if (kt < kt_end) compute(cur);
       if (kt + 1 < kt_end) {
-        nxt_a.store(As[cur ^ 1], tid);
-        nxt_b.store(Bs[cur ^ 1], tid);
+        nxt_a.store_masked(As[cur ^ 1], tid);
+        nxt_b.store_masked(Bs[cur ^ 1], tid);
       }
       __syncthreads();
     };
     if (kt_begin < kt_end) {
       load_into(ta0, tb0, kt_begin);
-      ta0.store(As[0], tid);
-      tb0.store(Bs[0], tid);
-      if (kt_begin + 1 < kt_end) load_into(ta1, tb1, kt_begin + 1);
+      load_into(ta1, tb1, min(kt_begin + 1, kt_end - 1));
+      ta0.store_masked(As[0], tid);
+      tb0.store_masked(Bs[0], tid);
       __syncthreads();
       for (int kt = kt_begin; kt < kt_end; kt += 2) {
         body(kt, 0, ta0, tb0, ta1, tb1);
-        if (kt + 1 < kt_end) body(kt + 1, 1, ta1, tb1, ta0, tb0);
+        body(kt + 1, 1, ta1, tb1, ta0, tb0);
       }
     }
   }
@@ -452,8 +515,32 @@ void launch_cfg(LaunchArgs& args, hipStream_t stream) {
                      stream, args);
 }
 
+// Whether the branch-free loads of the two-deep-prefetch configurations may
+// run on these operands: every piece float4-aligned, K a multiple of 4 where K
+// is the contiguous axis, and M, N multiples of 4 (hence >= 4) where they are.
+// Otherwise the launcher runs the configuration's one-deep twin.
+inline bool pf2_ok(const LaunchArgs& args, bool a_t, bool b_t) {
+  for (int i = 0; i < args.n_prob; ++i) {
+    const ProbDev& d = args.p[i];
+    if (d.M <= 0) continue;  // no tiles
+    if (d.N <= 0) return false;
+    if (a_t && d.M % 4 != 0) return false;
+    if (!b_t && d.N % 4 != 0) return false;
+    for (int pc = 0; pc < d.n_pieces; ++pc) {
+      if (!d.vecA[pc] || !d.vecB[pc]) return false;
+      if ((!a_t || b_t) && d.K[pc] % 4 != 0) return false;
+    }
+  }
+  return true;
+}
+
+// one-deep configuration standing in for a two-deep one (similar tile shape)
+constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3};
+static_assert(sizeof(kPf1Twin) / sizeof(kPf1Twin[0]) == kNumCfgs, "one twin per configuration");
+
 template <bool A_T, bool B_T, int GM>
 void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
+  if (cfg >= 0 && cfg < kNumCfgs && !pf2_ok(args, A_T, B_T)) cfg = kPf1Twin[cfg];
   switch (cfg) {
 #define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
   case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream); break;

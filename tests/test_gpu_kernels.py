@@ -340,29 +340,30 @@ N_GEMM_CFGS = 20  # tile configurations the library's tuner chooses from
 @pytest.mark.parametrize("cfg", range(N_GEMM_CFGS))
 def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
     """Each tile configuration, forced through the tuning table, in every operand
-    layout, with and without split-K, on a ragged shape (M, N, K not multiples
-    of any tile) with bias and ReLU."""
+    layout, with and without split-K, on ragged shapes (M, N, K not multiples
+    of any tile) with bias and ReLU: one with sizes off every multiple of 4
+    (the two-deep prefetch configurations run their one-deep twins there) and
+    one with sizes that are multiples of 4 (they run their branch-free loads,
+    with a K tail inside the last tile)."""
     a = api()
     rng = np.random.default_rng(cfg)
-    M, N, K = 333, 130, 77
     ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
-    bias = rng.standard_normal(N).astype(np.float32)
+    cases = [(M, N, K, ta, tb, splits) for M, N, K in ((333, 130, 77), (332, 132, 76))
+             for ta in (False, True) for tb in (False, True) for splits in (1, 3, 40)]
     try:
-        for ta in (False, True):
-            for tb in (False, True):
-                for splits in (1, 3, 40):
-                    key = f"{'T' if ta else 'N'}{'T' if tb else 'N'}|{M}x{N}x{K}"
-                    a.autotune_reset()
-                    a.autotune_set(key, cfg, splits)
-                    A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
-                    B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
-                    C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
-                    a.gemm(to_dev(A), to_dev(B), C, ta, tb, bias=to_dev(bias), relu=True, ws=ws)
-                    torch.cuda.synchronize()
-                    ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
-                    ref = np.maximum(ref + bias, 0.0)
-                    assert_close_array(C.cpu().numpy(), ref, 2e-6,
-                                       f"cfg {cfg} {key} splits {splits}")
+        for M, N, K, ta, tb, splits in cases:
+            key = f"{'T' if ta else 'N'}{'T' if tb else 'N'}|{M}x{N}x{K}"
+            a.autotune_reset()
+            a.autotune_set(key, cfg, splits)
+            A = rng.standard_normal((K, M) if ta else (M, K)).astype(np.float32)
+            B = rng.standard_normal((N, K) if tb else (K, N)).astype(np.float32)
+            bias = rng.standard_normal(N).astype(np.float32)
+            C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+            a.gemm(to_dev(A), to_dev(B), C, ta, tb, bias=to_dev(bias), relu=True, ws=ws)
+            torch.cuda.synchronize()
+            ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
+            ref = np.maximum(ref + bias, 0.0)
+            assert_close_array(C.cpu().numpy(), ref, 2e-6, f"cfg {cfg} {key} splits {splits}")
     finally:
         a.autotune_reset()
 

@@ -240,7 +240,9 @@ def test_c1_end_to_end_against_oracle_and_exact_optimum():
 def test_sage_bias_gradient_under_every_weight_gradient_plan(cfg):
     """The bias gradient is summed inside the weight-gradient GEMM by the first
     column tile: check db (and dWs) of a 2-layer SAGE model with every tile
-    configuration forced on those GEMMs, with and without split-K."""
+    configuration forced on those GEMMs, with and without split-K.  The same
+    configuration is forced on the step's other products too (the two-piece
+    [X | MX] forward and the input gradients), and every gradient is checked."""
     api, CPRAConfig, CPRASolver = mods()
     g = random_regular_graph(700, 5, 9)
     dg = api.DeviceGraph.from_csr(g)
@@ -254,22 +256,22 @@ def test_sage_bias_gradient_under_every_weight_gradient_plan(cfg):
     sol = CPRASolver(dg, cfgc, lam)
     sol.load_params(p)
     table = sol.autotune()
-    tn_keys = [e[0] for e in table if e[0].startswith("TN")]
-    assert tn_keys
+    keys = [e[0] for e in table]
+    assert any(k.startswith("TN") for k in keys) and any(not k.startswith("TN") for k in keys)
     try:
         for splits in (1, 4, 150):
             api.autotune_reset()
-            for k in tn_keys:
-                api.autotune_set(k, cfg, splits)
+            for k in keys:
+                api.autotune_set(k, cfg, splits if k.startswith("TN") else 1)
             sol.load_params(p)
             sol.step()
             torch.cuda.synchronize()
             gg = sol.unpack(sol.grads)
             for k in range(2):
-                assert_close_array(gg["layers"][k]["b"], go["layers"][k]["b"],
-                                   what=f"cfg {cfg} splits {splits} db{k}")
-                assert_close_array(gg["layers"][k]["Ws"], go["layers"][k]["Ws"],
-                                   what=f"cfg {cfg} splits {splits} dWs{k}")
+                for name in ("b", "Ws", "Wn"):
+                    assert_close_array(gg["layers"][k][name], go["layers"][k][name],
+                                       what=f"cfg {cfg} splits {splits} d{name}{k}")
+            assert_close_array(gg["emb"], go["emb"], what=f"cfg {cfg} splits {splits} dE")
     finally:
         api.autotune_reset()
         sol.close()
