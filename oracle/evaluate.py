@@ -5,6 +5,9 @@
   number of violated edges (both endpoints selected); a head is an
   independent set iff it violates no edge.
 * MaxCut: cut value sum_{i<j} A_ij [x_i != x_j] (the negated QUBO objective).
+* One instance per head (per-head edge weights [nnz, S]): head s is evaluated
+  on its own instance -- the edges whose weight in column s is nonzero, with
+  those weights; MIS violations and cut edges count those edges only.
 * DScore (Sec. 4.1 Evaluation Metrics):
   2 / (N S (S-1)) * sum_{s<l} d_H(x_s, x_l), from the pairwise Hamming
   distances themselves.
@@ -61,34 +64,51 @@ def dscore(X: np.ndarray) -> float:
     return 2.0 * pairwise_hamming_sum(X) / (N * S * (S - 1))
 
 
-def evaluate_one(X: np.ndarray, graph, problem: str, node_weight=None) -> Dict[str, object]:
-    """node_weight ([N] or [N, S], MIS only): also the total weight of each head's set."""
-    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+def evaluate_one(X: np.ndarray, graph, problem: str, node_weight=None,
+                 edge_weight=None) -> Dict[str, object]:
+    """node_weight ([N] or [N, S], MIS only): also the total weight of each head's set.
+    edge_weight ([nnz, S]): head s is evaluated on its own instance."""
     Xi = X.astype(np.int64)
+    N, S = X.shape
+    if edge_weight is None:
+        ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+        W = np.repeat(w[:, None], S, axis=1)   # every head on the graph itself
+        present = np.ones_like(W, dtype=bool)
+    else:
+        from .objective import instance_weights
+        ew = instance_weights(graph, edge_weight, S)
+        ei, ej, _ = edges_of(graph.row_ptr, graph.col_idx)
+        rp = np.asarray(graph.row_ptr, dtype=np.int64)
+        rows = np.repeat(np.arange(N, dtype=np.int64), np.diff(rp))
+        W = ew[rows < np.asarray(graph.col_idx, dtype=np.int64)]
+        present = W != 0
     out = {"pair_hamming": pairwise_hamming_sum(X)}
     if problem == "mis":
         out["size"] = Xi.sum(axis=0)
-        out["violations"] = (Xi[ei] * Xi[ej]).sum(axis=0)
+        out["violations"] = (Xi[ei] * Xi[ej] * present).sum(axis=0)
         from .objective import node_weights
         out["weight"] = (node_weights(node_weight, *X.shape) * Xi).sum(axis=0)
     elif problem == "maxcut":
-        differ = (Xi[ei] != Xi[ej])
+        differ = (Xi[ei] != Xi[ej]) & present
         out["cut_edges"] = differ.sum(axis=0).astype(np.int64)
-        out["cut"] = (w[:, None] * differ).sum(axis=0)
+        out["cut"] = (W * differ).sum(axis=0)
     else:
         raise ValueError(problem)
     return out
 
 
-def evaluate(X: np.ndarray, graph, problem: str, node_weight=None):
+def evaluate(X: np.ndarray, graph, problem: str, node_weight=None, edge_weight=None):
     """Per-graph evaluation; a single graph gives a one-element list."""
-    from .objective import _slice_graph
+    from .objective import _slice_graph, entry_range
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     res = []
     for g in range(gp.size - 1):
-        sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
-        nw = None if node_weight is None else np.asarray(node_weight)[gp[g]:gp[g + 1]]
-        res.append(evaluate_one(X[gp[g]:gp[g + 1]], sub, problem, nw))
+        lo, hi = int(gp[g]), int(gp[g + 1])
+        sub = _slice_graph(graph, lo, hi)
+        nw = None if node_weight is None else np.asarray(node_weight)[lo:hi]
+        a, b = entry_range(graph, lo, hi)
+        ew = None if edge_weight is None else np.asarray(edge_weight)[a:b]
+        res.append(evaluate_one(X[lo:hi], sub, problem, nw, ew))
     return res
 
 

@@ -13,6 +13,13 @@ Each edge {i, j} is counted once (i < j).  The relaxation (Sec. 2.2) keeps
 the same multilinear polynomial with p in [0,1]^N, so it equals the
 discrete objective on every binary point.
 
+Multiple instances (Sec. 3.1 lets every head s carry its own instance C_s;
+the multi-instance appendix solves 27 instances of one structure at once):
+with per-head edge weights ``edge_weight`` [nnz, S] (one value per CSR entry
+and head, symmetric), head s is the objective above on the graph whose edge
+weights are column s -- a zero weight leaves the edge out of that head's
+instance.  The annealing and diversity terms do not depend on the instances.
+
 CPRA loss (Sec. 3.1, Eq. CPRA-loss-function-GNN, and Sec. 3.3,
 Eq. CPRA-loss-function-GNN-variation):
   R(P) = sum_s l(P[:, s]; lam_s) + gamma * S(P) + nu * Psi(P)
@@ -81,6 +88,27 @@ def node_weights(node_weight, N: int, S: int) -> np.ndarray:
     return w
 
 
+def instance_weights(graph, edge_weight, S: int) -> np.ndarray:
+    """Per-head edge weights as [nnz, S] float64, checked to be symmetric
+    (entry (i, j) of head s equals entry (j, i))."""
+    rp = np.asarray(graph.row_ptr, dtype=np.int64)
+    ci = np.asarray(graph.col_idx, dtype=np.int64)
+    w = np.asarray(edge_weight, dtype=np.float64)
+    if w.shape != (ci.size, S):
+        raise ValueError("per-head edge weights must be [nnz, S]")
+    rows = np.repeat(np.arange(rp.size - 1, dtype=np.int64), np.diff(rp))
+    pos = {(int(i), int(j)): k for k, (i, j) in enumerate(zip(rows, ci))}
+    back = np.array([pos[(int(j), int(i))] for i, j in zip(rows, ci)], dtype=np.int64)
+    if back.size and not np.array_equal(w, w[back]):
+        raise ValueError("per-head edge weights must be symmetric")
+    return w
+
+
+def head_instance(graph, edge_weight: np.ndarray, s: int):
+    """Instance C_s of head s: the graph's pattern with edge weights edge_weight[:, s]."""
+    return _Sub(np.asarray(graph.row_ptr), np.asarray(graph.col_idx), edge_weight[:, s])
+
+
 def discrete_maxcut(x: np.ndarray, ei, ej, w) -> float:
     """sum_{i<j} A_ij (2 x_i x_j - x_i - x_j) for one binary vector."""
     x = np.asarray(x, dtype=np.float64)
@@ -144,23 +172,56 @@ def diversity_term(P: np.ndarray, ddof: int = 0) -> float:
 # ---------------------------------------------------------------------------
 
 def loss_terms(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
-               nu: float = 0.0, ddof: int = 0, node_weight=None) -> Dict[str, object]:
+               nu: float = 0.0, ddof: int = 0, node_weight=None,
+               edge_weight=None) -> Dict[str, object]:
     """All loss terms of one graph at logits Z [N, S].
 
     Returns {"head": l_hat_s [S], "entropy": S(P), "psi": Psi(P), "total": R}.
-    ``graph`` provides row_ptr, col_idx and weight (None = unweighted).
+    ``graph`` provides row_ptr, col_idx and weight (None = unweighted);
+    ``edge_weight`` [nnz, S], when given, replaces the graph's weights with one
+    instance per head (head s alone on the graph weighted by column s).
     """
-    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
     P, Q = sigmoid_pair(Z)
-    head = relaxed_head_losses(P, ei, ej, w, problem, lam, node_weight)
+    if edge_weight is None:
+        ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
+        head = relaxed_head_losses(P, ei, ej, w, problem, lam, node_weight)
+    else:
+        N, S = P.shape
+        ew = instance_weights(graph, edge_weight, S)
+        nw = None if node_weight is None else node_weights(node_weight, N, S)
+        head = np.zeros(S)
+        for s in range(S):
+            ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, ew[:, s])
+            head[s] = relaxed_head_losses(P[:, [s]], ei, ej, w, problem,
+                                          None if problem != "mis" else np.asarray(lam)[[s]],
+                                          None if nw is None else nw[:, [s]])[0]
     ent = entropy_term(P, Q, alpha)
     psi = diversity_term(P, ddof) if P.shape[1] > 1 else 0.0
     total = float(head.sum() + gamma * ent + nu * psi)
     return {"head": head, "entropy": ent, "psi": psi, "total": total}
 
 
+def _problem_grad(P: np.ndarray, graph, weight, problem: str, lam, node_weight) -> np.ndarray:
+    """d/dP of sum_s l_hat_s for the heads (columns) of P on one weighted graph."""
+    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, weight)
+    N, S = P.shape
+    # Neighbour sums by scattering each undirected edge to both endpoints.
+    nb = np.zeros((N, S), dtype=np.float64)
+    np.add.at(nb, ei, w[:, None] * P[ej])
+    np.add.at(nb, ej, w[:, None] * P[ei])
+    if problem == "mis":
+        return -node_weights(node_weight, N, S) + np.asarray(lam, dtype=np.float64)[None, :] * nb
+    if problem == "maxcut":
+        wdeg = np.zeros(N, dtype=np.float64)
+        np.add.at(wdeg, ei, w)
+        np.add.at(wdeg, ej, w)
+        return 2.0 * nb - wdeg[:, None]
+    raise ValueError(problem)
+
+
 def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: float,
-               alpha: int, nu: float = 0.0, ddof: int = 0, node_weight=None) -> np.ndarray:
+               alpha: int, nu: float = 0.0, ddof: int = 0, node_weight=None,
+               edge_weight=None) -> np.ndarray:
     """dR/dP [N, S] (derived by hand from the loss above).
 
     problem part: MIS    -w_is + lam_s * sum_{j in N(i)} A_ij P_js
@@ -169,21 +230,17 @@ def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: fl
     diversity:    nu * dPsi/dP_is = -nu * S (P_is - mu_i) / ((S - ddof) sigma_i),
                   taken as 0 where sigma_i = 0 (a subgradient of the norm).
     """
-    ei, ej, w = edges_of(graph.row_ptr, graph.col_idx, graph.weight)
     N, S = P.shape
-    # Neighbour sums by scattering each undirected edge to both endpoints.
-    nb = np.zeros((N, S), dtype=np.float64)
-    np.add.at(nb, ei, w[:, None] * P[ej])
-    np.add.at(nb, ej, w[:, None] * P[ei])
-    if problem == "mis":
-        g = -node_weights(node_weight, N, S) + np.asarray(lam, dtype=np.float64)[None, :] * nb
-    elif problem == "maxcut":
-        wdeg = np.zeros(N, dtype=np.float64)
-        np.add.at(wdeg, ei, w)
-        np.add.at(wdeg, ej, w)
-        g = 2.0 * nb - wdeg[:, None]
-    else:
-        raise ValueError(problem)
+    if edge_weight is None:
+        g = _problem_grad(P, graph, graph.weight, problem, lam, node_weight)
+    else:  # head s on its own instance
+        ew = instance_weights(graph, edge_weight, S)
+        nw = None if node_weight is None else node_weights(node_weight, N, S)
+        g = np.zeros((N, S))
+        for s in range(S):
+            g[:, [s]] = _problem_grad(P[:, [s]], graph, ew[:, s], problem,
+                                      None if problem != "mis" else np.asarray(lam)[[s]],
+                                      None if nw is None else nw[:, [s]])
     check_alpha(alpha)
     t = P - Q
     g = g - 2.0 * alpha * gamma * t ** (alpha - 1)
@@ -198,21 +255,31 @@ def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: fl
 
 
 def grad_wrt_Z(Z: np.ndarray, graph, problem: str, lam, gamma: float, alpha: int,
-               nu: float = 0.0, ddof: int = 0, node_weight=None) -> np.ndarray:
+               nu: float = 0.0, ddof: int = 0, node_weight=None, edge_weight=None) -> np.ndarray:
     """dR/dZ = dR/dP * P * (1 - P), with 1 - P taken as sigmoid(-Z)."""
     P, Q = sigmoid_pair(Z)
-    return grad_wrt_P(P, Q, graph, problem, lam, gamma, alpha, nu, ddof, node_weight) * P * Q
+    return grad_wrt_P(P, Q, graph, problem, lam, gamma, alpha, nu, ddof, node_weight,
+                      edge_weight) * P * Q
+
+
+def entry_range(graph, lo: int, hi: int):
+    """CSR entries [a, b) of rows lo..hi-1."""
+    rp = np.asarray(graph.row_ptr, dtype=np.int64)
+    return int(rp[lo]), int(rp[hi])
 
 
 def batched_loss_terms(Z: np.ndarray, graph, problem, lam, gamma, alpha, nu=0.0, ddof=0,
-                       node_weight=None):
+                       node_weight=None, edge_weight=None):
     """Per-graph loss terms of a block-diagonal batch (graph.graph_ptr slices)."""
     out = []
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
     for g in range(gp.size - 1):
-        sub = _slice_graph(graph, int(gp[g]), int(gp[g + 1]))
-        nw = None if node_weight is None else np.asarray(node_weight)[gp[g]:gp[g + 1]]
-        out.append(loss_terms(Z[gp[g]:gp[g + 1]], sub, problem, lam, gamma, alpha, nu, ddof, nw))
+        lo, hi = int(gp[g]), int(gp[g + 1])
+        sub = _slice_graph(graph, lo, hi)
+        nw = None if node_weight is None else np.asarray(node_weight)[lo:hi]
+        a, b = entry_range(graph, lo, hi)
+        ew = None if edge_weight is None else np.asarray(edge_weight)[a:b]
+        out.append(loss_terms(Z[lo:hi], sub, problem, lam, gamma, alpha, nu, ddof, nw, ew))
     return out
 
 

@@ -66,6 +66,7 @@ class StepConfig:
     eps: float = 1e-8
     weight_decay: float = 0.0
     node_weight: Optional[np.ndarray] = None  # MIS node weights [N] or [N, S]; None = 1
+    edge_weight: Optional[np.ndarray] = None  # one instance per head: [nnz, S]; None = the graph's
 
 
 def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=None,
@@ -76,22 +77,24 @@ def loss_and_grads(params, M, graph, cfg: StepConfig, gamma: float, relu_active=
     ``z_offset``: optional warm-start logits added to the output (see gnn.forward)."""
     Z, cache = gnn.forward(params, M, z_offset)
     gp = np.asarray(graph.graph_ptr, dtype=np.int64)
-    nw = cfg.node_weight
+    nw, ew = cfg.node_weight, cfg.edge_weight
     if gp.size > 2:
         terms = objective.batched_loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
-                                             cfg.nu, cfg.ddof, nw)
+                                             cfg.nu, cfg.ddof, nw, ew)
         dZ = np.zeros_like(Z)
         for g in range(gp.size - 1):
-            sub = objective._slice_graph(graph, int(gp[g]), int(gp[g + 1]))
-            nwg = None if nw is None else np.asarray(nw)[gp[g]:gp[g + 1]]
-            dZ[gp[g]:gp[g + 1]] = objective.grad_wrt_Z(Z[gp[g]:gp[g + 1]], sub, cfg.problem,
-                                                       cfg.lam, gamma, cfg.alpha, cfg.nu, cfg.ddof,
-                                                       nwg)
+            lo, hi = int(gp[g]), int(gp[g + 1])
+            sub = objective._slice_graph(graph, lo, hi)
+            nwg = None if nw is None else np.asarray(nw)[lo:hi]
+            a, b = objective.entry_range(graph, lo, hi)
+            ewg = None if ew is None else np.asarray(ew)[a:b]
+            dZ[lo:hi] = objective.grad_wrt_Z(Z[lo:hi], sub, cfg.problem, cfg.lam, gamma,
+                                             cfg.alpha, cfg.nu, cfg.ddof, nwg, ewg)
     else:
         terms = [objective.loss_terms(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha,
-                                      cfg.nu, cfg.ddof, nw)]
+                                      cfg.nu, cfg.ddof, nw, ew)]
         dZ = objective.grad_wrt_Z(Z, graph, cfg.problem, cfg.lam, gamma, cfg.alpha, cfg.nu,
-                                  cfg.ddof, nw)
+                                  cfg.ddof, nw, ew)
     grads = gnn.backward(params, M, cache, dZ, relu_active)
     if return_cache:
         return Z, terms, dZ, grads, cache
@@ -127,11 +130,14 @@ def loss_and_grads_per_graph(params, graph, cfg: StepConfig, gamma: float, relu_
              "layers": [{k: np.zeros_like(v) for k, v in L.items()} for L in params["layers"]]}
     terms = []
     nw = None if cfg.node_weight is None else np.asarray(cfg.node_weight)
+    ew = None if cfg.edge_weight is None else np.asarray(cfg.edge_weight)
     for b in range(gp.size - 1):
         lo, hi = int(gp[b]), int(gp[b + 1])
         sub = objective._slice_graph(graph, lo, hi)
         M = gnn.mean_aggregation_matrix(sub.row_ptr, sub.col_idx)
-        cfg_b = replace(cfg, node_weight=None if nw is None else nw[lo:hi])
+        ea, eb = objective.entry_range(graph, lo, hi)
+        cfg_b = replace(cfg, node_weight=None if nw is None else nw[lo:hi],
+                        edge_weight=None if ew is None else ew[ea:eb])
         ra = None if relu_active is None else [m[lo:hi] for m in relu_active]
         zo = None if z_offset is None else np.asarray(z_offset)[lo:hi]
         Zb, tb, dZb, gb = loss_and_grads(graph_params(params, b, lo, hi), M, sub, cfg_b, gamma,

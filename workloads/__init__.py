@@ -16,6 +16,7 @@ from .graphs import (  # noqa: F401
     disjoint_union,
     induced_subgraph,
     bfs_ball,
+    instance_edge_weights,
 )
 from .params import init_mpnn_params, init_params, init_params_per_graph, param_shapes, \
     random_channels  # noqa: F401

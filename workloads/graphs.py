@@ -301,3 +301,35 @@ def induced_subgraph(g: CSRGraph, nodes: np.ndarray) -> CSRGraph:
     keep = (remap[u] >= 0) & (remap[v] >= 0)
     return csr_from_edges(nodes.size, remap[u[keep]], remap[v[keep]],
                           None if w is None else w[keep])
+
+
+def instance_edge_weights(g: CSRGraph, S: int, seed: int, kind: str = "uniform",
+                          drop: float = 0.0) -> np.ndarray:
+    """S weighted instances on the pattern of g, one per head: float32 [nnz, S],
+    symmetric (both CSR entries of an edge carry the same S values).
+
+    kind: "uniform" U(0.5, 1.5), "signed" +-1 with equal odds (Gset-style
+    couplings), "integer" U{1, ..., 4}.  drop: fraction of (edge, head) pairs set
+    to 0, i.e. the edge is absent from that head's instance."""
+    rng = np.random.default_rng(seed)
+    n = g.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), g.degrees())
+    cols = g.col_idx.astype(np.int64)
+    upper = rows < cols
+    E = int(upper.sum())
+    if kind == "uniform":
+        vals = rng.uniform(0.5, 1.5, (E, S))
+    elif kind == "signed":
+        vals = np.where(rng.random((E, S)) < 0.5, -1.0, 1.0)
+    elif kind == "integer":
+        vals = rng.integers(1, 5, (E, S)).astype(np.float64)
+    else:
+        raise ValueError(kind)
+    if drop > 0:
+        vals[rng.random((E, S)) < drop] = 0.0
+    # edge id of every CSR entry: its position among the upper entries (i < j)
+    keys = rows[upper] * n + cols[upper]
+    lo = np.minimum(rows, cols)
+    hi = np.maximum(rows, cols)
+    eid = np.searchsorted(keys, lo * n + hi)
+    return vals[eid].astype(np.float32)
