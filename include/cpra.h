@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 5
+#define CPRA_ABI_VERSION 6
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -166,6 +166,10 @@ cpra_status cpra_gemm_grouped(const cpra_csr* g, int32_t mode, int32_t trans_b, 
  *           (w = 1 unless node weights are given: weighted MIS, one weight
  *           vector per head for the multi-task form of the two-stage appendix)
  *   MaxCut: l_s = sum_{i<j} A_ij (2 P_is P_js - P_is - P_js)
+ *   with A_ij the graph's weight (1 when it has none) or, with per-head edge
+ *   weights, A_ijs: one instance C_s per head on the graph's pattern (Sec. 3.1
+ *   solves S instances at once; the multi-instance appendix, 27 instances of
+ *   one structure), a zero leaving the edge out of head s's instance.
  *   Psi    = -S * sum_i STD_s[P_is]  (population STD, or sample STD if std_ddof = 1)
  * Output dZ = dR/dZ and, per graph g of the batch, terms[g*(S+2) + c]:
  *   c < S: l_c of graph g;  c = S: sum of (1-(2P-1)^alpha) over the graph;
@@ -191,6 +195,15 @@ typedef struct {
    * CPRA_ERR_PARAM for MaxCut. */
   const float* node_weight;
   int64_t ld_node_weight;
+  /* Optional per-head edge weights (device), one instance per head:
+   * A_ijs = edge_weight[e * ld_edge_weight + s] for CSR entry e = (i, j),
+   * ld_edge_weight >= S.  They replace g->weight in the objective (the GNN's
+   * mean aggregation is over the pattern either way) and must be symmetric
+   * (entries (i, j) and (j, i) equal for every head; not checked on the
+   * device).  MaxCut then uses each head's own weighted degree, summed in
+   * the same pass, so g->wdeg is not read.  NULL: A_ijs = A_ij for every s. */
+  const float* edge_weight;
+  int64_t ld_edge_weight;
 } cpra_loss_cfg;
 
 size_t cpra_loss_workspace_bytes(const cpra_csr* g, const cpra_loss_cfg* cfg);
@@ -331,6 +344,9 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
  *   MaxCut: value = |{i<j in E : x_is != x_js}| (cut edges), violations = 0,
  *           wvalue = sum of A_ij over cut edges (FP64, fixed-order sums)
  *   pair_hamming[g] = sum_{s<l} d_H(x_s, x_l) = sum_i k_i (S - k_i), k_i = sum_s x_is.
+ * With per-head edge weights (edge_weight as in cpra_loss_cfg, or NULL) head s
+ * is evaluated on its own instance: E is then the set of edges whose weight
+ * in head s is nonzero, and A_ij is that weight.
  * X [N,S] uint8 (ldx), value/violations [n_graphs*S] int64, wvalue
  * [n_graphs*S] double, pair_hamming [n_graphs] int64: each may be NULL.
  * Integer results are exact.
@@ -340,6 +356,7 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
                             int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
                             int64_t* violations, double* wvalue, int64_t* pair_hamming,
                             const float* node_weight, int64_t ld_node_weight,
+                            const float* edge_weight, int64_t ld_edge_weight,
                             void* ws, size_t ws_bytes, cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------

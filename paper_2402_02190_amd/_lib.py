@@ -37,7 +37,8 @@ class LossCfg(C.Structure):
                 ("std_ddof", C.c_int32), ("gamma", C.c_float), ("nu", C.c_float),
                 ("lambda_", C.c_void_p), ("step_counter", C.c_void_p),
                 ("gamma_start", C.c_float), ("gamma_end", C.c_float), ("T", C.c_int32),
-                ("node_weight", C.c_void_p), ("ld_node_weight", C.c_int64)]
+                ("node_weight", C.c_void_p), ("ld_node_weight", C.c_int64),
+                ("edge_weight", C.c_void_p), ("ld_edge_weight", C.c_int64)]
 
 
 class ModelCfg(C.Structure):
@@ -98,7 +99,8 @@ PROTOTYPES = {
     "cpra_train_step_workspace_bytes": (SZ, [PCsr, PStep]),
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),
     "cpra_round_eval_workspace_bytes": (SZ, [PCsr, I32]),
-    "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, I64, P, SZ, P]),
+    "cpra_round_eval": (None, [PCsr, I32, I32, P, I64, P, I64, P, P, P, P, P, I64, P, I64, P, SZ,
+                               P]),
     "cpra_pairwise_hamming_workspace_bytes": (SZ, [I32, I32]),
     "cpra_pairwise_hamming": (None, [I32, I32, P, I64, P, I64, P, P, P, SZ, P]),
     "cpra_node_features": (None, [PCsr, I32, I32, P, I64, P, I64, P, P]),

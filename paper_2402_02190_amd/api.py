@@ -177,16 +177,29 @@ def _node_weight_args(node_weight: Optional[torch.Tensor]):
     return node_weight.data_ptr(), node_weight.stride(0)
 
 
+def _edge_weight_args(edge_weight: Optional[torch.Tensor]):
+    """(pointer, leading dimension) of per-head edge weights [nnz, S]."""
+    if edge_weight is None:
+        return None, 0
+    _dev_f32(edge_weight, "edge_weight")
+    if edge_weight.dim() != 2:
+        raise ValueError("edge_weight must be [nnz, S]")
+    return edge_weight.data_ptr(), edge_weight.stride(0)
+
+
 def make_loss_cfg(problem: int, S: int, lam: Optional[torch.Tensor], alpha: int = 2,
                   gamma: float = 0.0, nu: float = 0.0, std_ddof: int = 0,
                   step_counter: Optional[torch.Tensor] = None, gamma_start: float = 0.0,
                   gamma_end: float = 0.0, T: int = 1,
-                  node_weight: Optional[torch.Tensor] = None) -> LossCfg:
-    """node_weight: optional MIS node weights, float32 [N] or [N, S] on the device
-    (the caller keeps the tensors alive while the config is used)."""
+                  node_weight: Optional[torch.Tensor] = None,
+                  edge_weight: Optional[torch.Tensor] = None) -> LossCfg:
+    """node_weight: optional MIS node weights, float32 [N] or [N, S] on the device;
+    edge_weight: optional per-head edge weights, float32 [nnz, S] (one instance per
+    head; symmetric).  The caller keeps the tensors alive while the config is used."""
     nw, ld = _node_weight_args(node_weight)
+    ew, lde = _edge_weight_args(edge_weight)
     return LossCfg(problem, S, alpha, std_ddof, gamma, nu, _ptr(lam), _ptr(step_counter),
-                   gamma_start, gamma_end, T, nw, ld)
+                   gamma_start, gamma_end, T, nw, ld, ew, lde)
 
 
 def loss_workspace_bytes(g, cfg: LossCfg) -> int:
@@ -288,14 +301,16 @@ def round_eval_workspace_bytes(g, S: int) -> int:
 
 
 def round_eval(g, problem: int, Z: torch.Tensor, X=None, value=None, violations=None,
-               wvalue=None, pair_hamming=None, ws=None, stream=None, node_weight=None):
+               wvalue=None, pair_hamming=None, ws=None, stream=None, node_weight=None,
+               edge_weight=None):
     S = Z.shape[1]
     if ws is None:
         ws = torch.empty(round_eval_workspace_bytes(g, S), dtype=torch.uint8, device=Z.device)
     nw, ld = _node_weight_args(node_weight)
+    ew, lde = _edge_weight_args(edge_weight)
     call("cpra_round_eval", _csr(g), problem, S, _ptr(Z), Z.stride(0), _ptr(X),
          0 if X is None else X.stride(0), _ptr(value), _ptr(violations), _ptr(wvalue),
-         _ptr(pair_hamming), nw, ld, _ptr(ws), ws.numel(), _stream(stream))
+         _ptr(pair_hamming), nw, ld, ew, lde, _ptr(ws), ws.numel(), _stream(stream))
 
 
 def pairwise_hamming(X: torch.Tensor, D: Optional[torch.Tensor] = None,

@@ -7,7 +7,9 @@
 // smaller endpoint only.  Integer counts are summed per block and added with
 // 64-bit integer atomics (exact, so order does not matter); weighted values
 // (the cut weight of MaxCut, the set weight of weighted MIS) go through
-// per-item FP64 partials and the fixed-order segmented reduction.
+// per-item FP64 partials and the fixed-order segmented reduction.  With
+// per-head edge weights head s is evaluated on its own instance: only edges
+// with a nonzero weight in head s count, with that weight.
 #include "common.hpp"
 
 namespace cpra {
@@ -34,6 +36,8 @@ struct EvalArgs {
   int R;
   const float* node_w;  // MIS node weights or null (weight 1)
   int64_t ld_nw;        // 0: one weight per node
+  const float* edge_w;  // per-head edge weights [nnz, ld_ew] or null
+  int64_t ld_ew;
 };
 
 template <typename T>
@@ -93,11 +97,13 @@ __global__ __launch_bounds__(256) void k_round_eval(EvalArgs a) {
       for (int k = beg; k < end; ++k) {
         const int j = a.col_idx[k];
         if (j <= row) continue;
-        const float w = a.weight ? a.weight[k] : 1.0f;
+        const float w0 = a.weight ? a.weight[k] : 1.0f;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const int s = c * lpr + cl;
           if (s >= S) continue;
+          const float w = a.edge_w ? a.edge_w[(int64_t)k * a.ld_ew + s] : w0;
+          if (a.edge_w && w == 0.0f) continue;  // not an edge of head s's instance
           const int xj = a.Z[(int64_t)j * a.ldz + s] > 0.0f ? 1 : 0;
           if (mis) {
             c_vio[c] += x[c] & xj;
@@ -191,7 +197,8 @@ size_t cpra_round_eval_workspace_bytes(const cpra_csr* g, int32_t S) {
 cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const float* Z,
                             int64_t ldz, uint8_t* X, int64_t ldx, int64_t* value,
                             int64_t* violations, double* wvalue, int64_t* pair_hamming,
-                            const float* node_weight, int64_t ld_node_weight, void* ws,
+                            const float* node_weight, int64_t ld_node_weight,
+                            const float* edge_weight, int64_t ld_edge_weight, void* ws,
                             size_t ws_bytes, cpra_stream_t stream) {
   using namespace cpra;
   CPRA_CHECK(check_csr(g, "round_eval", false, false));
@@ -204,6 +211,8 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
     CPRA_FAIL(CPRA_ERR_PARAM, "round_eval: node weights are defined for MIS only");
   if (node_weight && ld_node_weight != 0 && ld_node_weight < S)
     CPRA_FAIL(CPRA_ERR_SHAPE, "round_eval: ld_node_weight must be 0 or >= S");
+  if (edge_weight && ld_edge_weight < S)
+    CPRA_FAIL(CPRA_ERR_SHAPE, "round_eval: ld_edge_weight must be >= S");
   size_t item_off, part_off;
   size_t need = eval_ws(g, S, &item_off, &part_off);
   if (ws == nullptr || ws_bytes < need)
@@ -240,10 +249,12 @@ cpra_status cpra_round_eval(const cpra_csr* g, int32_t problem, int32_t S, const
   a.R = G.R;
   a.node_w = node_weight;
   a.ld_nw = ld_node_weight;
+  a.edge_w = edge_weight;
+  a.ld_ew = ld_edge_weight;
   const int blocks = (int)G.items_cap;
   ProfScope ps("round_eval", st, 0.0,
                4.0 * (double)g->n_nodes * S + (X ? (double)g->n_nodes * S : 0.0) +
-                   4.0 * (double)g->nnz + 4.0 * g->n_nodes);
+                   4.0 * (double)g->nnz * (edge_weight ? 1.0 + S : 1.0) + 4.0 * g->n_nodes);
   switch (G.nc) {
 #define CPRA_EVAL_CASE(NCV)                                                          \
   case NCV:                                                                          \

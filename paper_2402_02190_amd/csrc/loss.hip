@@ -6,6 +6,9 @@
 //           (node weights w, 1 by default)
 //   MaxCut: l_is = P_is ((AP)_is - wdeg_i),          dl/dP_is = 2 (AP)_is - wdeg_i
 // so that sum_i l_is equals the per-head objective with every edge counted once.
+// With one instance per head (per-head edge weights A_ijs, template flag PH)
+// the gathers read A_ijs beside P_js, and MaxCut's wdeg_is = sum_j A_ijs is
+// summed in the same pass.
 //   annealing: phi_is = 1 - t^alpha, t = 2P - 1 = P - Q (Q = sigmoid(-Z)),
 //              evaluated as 4 P Q sum_{k<alpha/2} t^(2k); d(gamma phi)/dP = -2 alpha gamma t^(alpha-1)
 //   diversity: Psi_i = -S sigma_i over the heads of node i,
@@ -51,6 +54,8 @@ struct LossArgs {
   int64_t items_cap;
   const float* node_w;  // MIS node weights or null
   int64_t ld_nw;        // 0: one weight per node
+  const float* edge_w;  // per-head edge weights [nnz, ld_ew] (PH) or null
+  int64_t ld_ew;
 };
 
 __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
@@ -58,7 +63,7 @@ __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
   return v;
 }
 
-template <int NC>
+template <int NC, bool PH>
 __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   int g, r0, r1;
   if (!item_rows(blockIdx.x, a.n_graphs, a.n, a.graph_ptr, a.item_ptr, a.R, &g, &r0, &r1)) return;
@@ -99,12 +104,13 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   for (int base = r0; base < r1; base += rows_per_iter) {
     const int row = base + wave * rpw + sub;
     const bool active = row < r1;
-    float z[NC], ap[NC];
+    float z[NC], ap[NC], wdh[NC];  // wdh: per-head weighted degree (PH)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int s = c * lpr + cl;
       z[c] = (active && s < S) ? a.Z[(int64_t)row * a.ldz + s] : 0.0f;
       ap[c] = 0.0f;
+      wdh[c] = 0.0f;
     }
     if (active) {
       // Neighbours in full chunks of 4 (index and weight loads, then the four
@@ -124,10 +130,23 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
             const float p1 = a.P[(int64_t)j1 * a.ldp + s];
             const float p2 = a.P[(int64_t)j2 * a.ldp + s];
             const float p3 = a.P[(int64_t)j3 * a.ldp + s];
-            ap[c] += w0 * p0;
-            ap[c] += w1 * p1;
-            ap[c] += w2 * p2;
-            ap[c] += w3 * p3;
+            if constexpr (PH) {
+              const float* e = a.edge_w + (int64_t)k * a.ld_ew + s;
+              const float v0 = e[0], v1 = e[a.ld_ew], v2 = e[2 * a.ld_ew], v3 = e[3 * a.ld_ew];
+              ap[c] += v0 * p0;
+              ap[c] += v1 * p1;
+              ap[c] += v2 * p2;
+              ap[c] += v3 * p3;
+              wdh[c] += v0;
+              wdh[c] += v1;
+              wdh[c] += v2;
+              wdh[c] += v3;
+            } else {
+              ap[c] += w0 * p0;
+              ap[c] += w1 * p1;
+              ap[c] += w2 * p2;
+              ap[c] += w3 * p3;
+            }
           }
         }
       }
@@ -151,14 +170,27 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
             const float p1 = a.P[(int64_t)j1 * a.ldp + s];
             const float p2 = a.P[(int64_t)j2 * a.ldp + s];
             // padded entries add an exact zero (weight 0 by a select, no branch)
-            ap[c] += w0 * p0;
-            ap[c] += (n_left > 1 ? w1 : 0.f) * p1;
-            ap[c] += (n_left > 2 ? w2 : 0.f) * p2;
+            if constexpr (PH) {
+              const float* e = a.edge_w + s;
+              const float v0 = e[(int64_t)k * a.ld_ew];
+              const float v1 = n_left > 1 ? e[(int64_t)min(k + 1, end - 1) * a.ld_ew] : 0.f;
+              const float v2 = n_left > 2 ? e[(int64_t)min(k + 2, end - 1) * a.ld_ew] : 0.f;
+              ap[c] += v0 * p0;
+              ap[c] += v1 * p1;
+              ap[c] += v2 * p2;
+              wdh[c] += v0;
+              wdh[c] += v1;
+              wdh[c] += v2;
+            } else {
+              ap[c] += w0 * p0;
+              ap[c] += (n_left > 1 ? w1 : 0.f) * p1;
+              ap[c] += (n_left > 2 ? w2 : 0.f) * p2;
+            }
           }
         }
       }
     }
-    const float wd = (active && !mis) ? a.wdeg[row] : 0.0f;
+    const float wd = (!PH && active && !mis) ? a.wdeg[row] : 0.0f;
 
     float p[NC], q[NC];
 #pragma unroll
@@ -211,8 +243,9 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
         l = p[c] * (u + 0.5f * lam_h[c] * ap[c]);
         gr = u + lam_h[c] * ap[c];
       } else {
-        l = p[c] * (ap[c] - wd);
-        gr = 2.0f * ap[c] - wd;
+        const float wdc = PH ? wdh[c] : wd;
+        l = p[c] * (ap[c] - wdc);
+        gr = 2.0f * ap[c] - wdc;
       }
       gr -= two_alpha_gamma * t_am1;
       if (diverse) gr += a.nu * inv_dev_scale * (p[c] - mu);
@@ -317,6 +350,8 @@ cpra_status check_loss_cfg(const cpra_csr* g, const cpra_loss_cfg* cfg) {
     CPRA_FAIL(CPRA_ERR_PARAM, "loss: node weights are defined for MIS only");
   if (cfg->node_weight && cfg->ld_node_weight != 0 && cfg->ld_node_weight < cfg->S)
     CPRA_FAIL(CPRA_ERR_SHAPE, "loss: ld_node_weight must be 0 or >= S");
+  if (cfg->edge_weight && cfg->ld_edge_weight < cfg->S)
+    CPRA_FAIL(CPRA_ERR_SHAPE, "loss: ld_edge_weight must be >= S");
   return CPRA_OK;
 }
 
@@ -379,19 +414,25 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.items_cap = G.items_cap;
   a.node_w = cfg->node_weight;
   a.ld_nw = cfg->ld_node_weight;
+  a.edge_w = cfg->edge_weight;
+  a.ld_ew = cfg->ld_edge_weight;
+  const bool ph = cfg->edge_weight != nullptr;
   const int blocks = (int)G.items_cap;
   // compulsory bytes: Z and P read once, dZ written, CSR (+weights), wdeg, partials
   const double ns4 = 4.0 * (double)g->n_nodes * S;
-  const double loss_bytes = ns4 * (dZ ? 3.0 : 2.0) + 4.0 * (double)g->nnz * (g->weight ? 2.0 : 1.0) +
-                            4.0 * (double)g->n_nodes * (cfg->problem == CPRA_MAXCUT ? 2.0 : 1.0) +
+  const double loss_bytes = ns4 * (dZ ? 3.0 : 2.0) +
+                            4.0 * (double)g->nnz * (g->weight && !ph ? 2.0 : 1.0) +
+                            4.0 * (double)g->n_nodes * (cfg->problem == CPRA_MAXCUT && !ph ? 2.0 : 1.0) +
                             (cfg->node_weight ? 4.0 * (double)g->n_nodes *
                                                     (cfg->ld_node_weight ? S : 1) : 0.0) +
+                            (ph ? 4.0 * (double)g->nnz * S : 0.0) +
                             4.0 * (double)(S + 2) * G.items_cap;
   ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes);
   switch (G.nc) {
 #define CPRA_LOSS_CASE(NCV)                                                             \
   case NCV:                                                                             \
-    hipLaunchKernelGGL(k_loss<NCV>, dim3(blocks), dim3(256), 0, stream, a);             \
+    if (ph) hipLaunchKernelGGL((k_loss<NCV, true>), dim3(blocks), dim3(256), 0, stream, a); \
+    else hipLaunchKernelGGL((k_loss<NCV, false>), dim3(blocks), dim3(256), 0, stream, a);   \
     break;
     CPRA_LOSS_CASE(1)
     CPRA_LOSS_CASE(2)
@@ -432,7 +473,8 @@ size_t cpra_loss_workspace_bytes(const cpra_csr* g, const cpra_loss_cfg* cfg) {
 cpra_status cpra_loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const float* Z,
                               int64_t ldz, const float* P, int64_t ldp, float* dZ, int64_t lddz,
                               double* terms, void* ws, size_t ws_bytes, cpra_stream_t stream) {
-  CPRA_CHECK(cpra::check_csr(g, "loss_fwd_bwd", false, cfg && cfg->problem == CPRA_MAXCUT));
+  CPRA_CHECK(cpra::check_csr(g, "loss_fwd_bwd", false,
+                             cfg && cfg->problem == CPRA_MAXCUT && cfg->edge_weight == nullptr));
   CPRA_CHECK(cpra::check_loss_cfg(g, cfg));
   if (g->n_nodes > 0) {
     if (Z == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "loss_fwd_bwd: Z is NULL");

@@ -519,7 +519,8 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   using namespace cpra;
   if (cfg == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "train_step: cfg is NULL");
   CPRA_CHECK(check_graph_and_model(g, &cfg->model, "train_step"));
-  if (cfg->loss.problem == CPRA_MAXCUT && g->n_nodes > 0 && g->wdeg == nullptr)
+  if (cfg->loss.problem == CPRA_MAXCUT && cfg->loss.edge_weight == nullptr && g->n_nodes > 0 &&
+      g->wdeg == nullptr)
     CPRA_FAIL(CPRA_ERR_NULL, "train_step: wdeg is NULL (run cpra_csr_prepare)");
   cpra_loss_cfg lc = cfg->loss;
   lc.step_counter = step_counter;

@@ -54,11 +54,17 @@ def gamma_schedule(t: int, T: int, g0: float, g1: float) -> float:
 
 class CPRASolver:
     """z_offset (optional): float32 [N, S] device tensor of fixed logits added to the
-    GNN's output (a learned warm start); the solver keeps a reference to it."""
+    GNN's output (a learned warm start); the solver keeps a reference to it.
+    node_weight (optional, MIS): node weights [N] or [N, S].
+    edge_weight (optional): per-head edge weights [nnz, S], symmetric -- one instance
+    per head on the graph's pattern (a zero leaves the edge out of that head's
+    instance); they replace the graph's own weights in the objective and the
+    evaluation."""
 
     def __init__(self, graph: DeviceGraph, cfg: CPRAConfig, lam=None, device="cuda",
                  z_offset: Optional[torch.Tensor] = None,
-                 node_weight: Optional[np.ndarray] = None):
+                 node_weight: Optional[np.ndarray] = None,
+                 edge_weight: Optional[np.ndarray] = None):
         if cfg.problem not in ("mis", "maxcut"):
             raise ValueError("problem must be 'mis' or 'maxcut'")
         self.graph = graph
@@ -92,9 +98,15 @@ class CPRASolver:
             if nw.shape not in ((N,), (N, S)):
                 raise ValueError(f"node weights must be [{N}] or [{N}, {S}]")
             self.node_weight = torch.from_numpy(nw).to(device)
+        self.edge_weight = None  # one instance per head: float32 [nnz, S]
+        if edge_weight is not None:
+            ew = np.ascontiguousarray(edge_weight, dtype=np.float32)
+            if ew.shape != (graph.nnz, S):
+                raise ValueError(f"per-head edge weights must be [{graph.nnz}, {S}]")
+            self.edge_weight = torch.from_numpy(ew).to(device)
         self.loss_cfg = api.make_loss_cfg(self.problem_id, S, self.lam, cfg.alpha, 0.0, cfg.nu,
                                           cfg.std_ddof, None, cfg.gamma_start, cfg.gamma_end, cfg.T,
-                                          self.node_weight)
+                                          self.node_weight, self.edge_weight)
         self.adam_cfg = api.AdamCfg(cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay)
         self.step_cfg = api.StepCfg(self.model_cfg, self.loss_cfg, self.adam_cfg)
         self.n_params = api.model_param_count(self.model_cfg, N)
@@ -269,10 +281,11 @@ class CPRASolver:
         value = torch.empty(G * S, dtype=torch.int64, device=dev)
         viol = torch.empty(G * S, dtype=torch.int64, device=dev)
         ph = torch.empty(G, dtype=torch.int64, device=dev)
-        weighted = self.graph.weight is not None or self.node_weight is not None
+        weighted = (self.graph.weight is not None or self.node_weight is not None or
+                    self.edge_weight is not None)
         wv = torch.empty(G * S, dtype=torch.float64, device=dev) if weighted else None
         api.round_eval(self.graph, self.problem_id, Z, X, value, viol, wv, ph,
-                       node_weight=self.node_weight)
+                       node_weight=self.node_weight, edge_weight=self.edge_weight)
         torch.cuda.synchronize()
         out = {"X": X[: self.graph.n].cpu().numpy(), "value": value.cpu().numpy().reshape(G, S),
                "violations": viol.cpu().numpy().reshape(G, S), "pair_hamming": ph.cpu().numpy()}

@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = _lib.lib()
-    assert lib.cpra_abi_version() == 5
+    assert lib.cpra_abi_version() == 6
     for code, name in _lib.STATUS.items():
         assert lib.cpra_status_string(code).decode() == name
 
@@ -54,9 +54,9 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(cpra_csr), sizeof(cpra_loss_cfg), sizeof(cpra_model_cfg),
          sizeof(cpra_adam_cfg), sizeof(cpra_step_cfg));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(cpra_csr, inv_deg), offsetof(cpra_loss_cfg, lambda),
+  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(cpra_csr, inv_deg), offsetof(cpra_loss_cfg, lambda),
          offsetof(cpra_loss_cfg, step_counter), offsetof(cpra_loss_cfg, T),
-         offsetof(cpra_step_cfg, adam));
+         offsetof(cpra_step_cfg, adam), offsetof(cpra_loss_cfg, edge_weight));
   return 0;
 }
 """)
@@ -69,7 +69,8 @@ int main(void) {
     assert sizes == [C.sizeof(_lib.Csr), C.sizeof(_lib.LossCfg), C.sizeof(_lib.ModelCfg),
                      C.sizeof(_lib.AdamCfg), C.sizeof(_lib.StepCfg)]
     assert offs == [_lib.Csr.inv_deg.offset, _lib.LossCfg.lambda_.offset,
-                    _lib.LossCfg.step_counter.offset, _lib.LossCfg.T.offset, _lib.StepCfg.adam.offset]
+                    _lib.LossCfg.step_counter.offset, _lib.LossCfg.T.offset, _lib.StepCfg.adam.offset,
+                    _lib.LossCfg.edge_weight.offset]
 
 
 def _validate(rp, ci, w=None):
@@ -166,6 +167,10 @@ def test_host_argument_errors_need_no_gpu():
     assert lib.cpra_loss_fwd_bwd(C.byref(big), C.byref(ok_cfg), 8, 4, None, 0, None, 0, None,
                                  None, 0, None) == 5
     assert lib.cpra_gemm(0, 0, -1, 4, 4, 8, 4, 8, 4, 0.0, 8, 4, None, 0, None, 0, None) == 2
+    ew_cfg = api.make_loss_cfg(api.MAXCUT, 4, None)
+    ew_cfg.edge_weight, ew_cfg.ld_edge_weight = 8, 3  # leading dimension below S
+    assert lib.cpra_loss_fwd_bwd(C.byref(csr), C.byref(ew_cfg), 8, 4, None, 0, None, 0, None,
+                                 None, 0, None) == 2
     ddof_cfg = api.make_loss_cfg(api.MAXCUT, 1, None, nu=0.5, std_ddof=1)
     assert lib.cpra_loss_fwd_bwd(C.byref(csr), C.byref(ddof_cfg), 8, 1, None, 0, None, 0, None,
                                  None, 0, None) == 4
