@@ -248,3 +248,14 @@ def test_multi_instance_train_step_matches_oracle(case):
     assert torch.equal(ea.params, gr.params) and torch.equal(ea.terms, gr.terms)
     ea.close()
     gr.close()
+
+
+@pytest.mark.parametrize("problem", ["maxcut", "mis"])
+def test_together_vs_one_by_one_driver_runs(problem):
+    """The comparison driver on tiny instances: both arms train and score every instance."""
+    from paper_2402_02190_amd import multiinstance
+    res = multiinstance.run(problem, instances=3, n=60, degree=3, hidden=8, T=40, seed=1)
+    assert res["instances"] == 3
+    assert res["together_seconds"] > 0 and res["one_by_one_seconds"] > 0
+    assert res["together_better"] + res["equal"] + res["one_by_one_better"] == 3
+    assert res["mean_score_together"] >= 0 and res["mean_score_one_by_one"] >= 0

@@ -309,8 +309,9 @@ def instance_edge_weights(g: CSRGraph, S: int, seed: int, kind: str = "uniform",
     symmetric (both CSR entries of an edge carry the same S values).
 
     kind: "uniform" U(0.5, 1.5), "signed" +-1 with equal odds (Gset-style
-    couplings), "integer" U{1, ..., 4}.  drop: fraction of (edge, head) pairs set
-    to 0, i.e. the edge is absent from that head's instance."""
+    couplings), "integer" U{1, ..., 4}, "unit" 1 (with drop: an edge subset per
+    head).  drop: fraction of (edge, head) pairs set to 0, i.e. the edge is
+    absent from that head's instance."""
     rng = np.random.default_rng(seed)
     n = g.n
     rows = np.repeat(np.arange(n, dtype=np.int64), g.degrees())
@@ -323,6 +324,8 @@ def instance_edge_weights(g: CSRGraph, S: int, seed: int, kind: str = "uniform",
         vals = np.where(rng.random((E, S)) < 0.5, -1.0, 1.0)
     elif kind == "integer":
         vals = rng.integers(1, 5, (E, S)).astype(np.float64)
+    elif kind == "unit":
+        vals = np.ones((E, S))
     else:
         raise ValueError(kind)
     if drop > 0:
