@@ -58,3 +58,36 @@ def test_measure_scales_each_counter_by_the_calibration_copy(tmp_path, monkeypat
     assert TR.load_traffic("gemm_nn_64x64x16_w2x2", "C4", str(prof)) is None
     monkeypatch.setattr(TR, "source_hash", lambda fam: "changed")
     assert TR.load_traffic("gemm_nn_64x64x16_w2x2", "C2", str(prof)) is None
+
+
+def test_mfma_counter_summary_on_a_synthetic_pass(tmp_path):
+    """MFMA utilisation = busy cycles / (SIMDs x clock x duration), per instantiation."""
+    from paper_2402_02190_amd import mfma_counters as mc
+    d = tmp_path / "sq"
+    d.mkdir()
+    name = "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 2, 0>(cpra::gemmk::LaunchArgs)"
+    rows = []
+    for disp, ns in ((1, 10000), (2, 20000)):  # 10 and 20 us
+        busy = 0.5 * mc.N_SIMD * mc.CLOCK_HZ * ns * 1e-9  # half busy
+        vals = {"SQ_WAVE_CYCLES": 1000.0, "SQ_BUSY_CYCLES": 10.0, "SQ_VALU_MFMA_BUSY_CYCLES": busy,
+                "SQ_INSTS_MFMA": busy / 64, "SQ_WAIT_INST_LDS": 100.0, "SQ_LDS_BANK_CONFLICT": 5.0,
+                "SQ_ACTIVE_INST_LDS": 50.0, "SQ_WAIT_INST_ANY": 400.0}
+        for c, v in vals.items():
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": c, "Counter_Value": v,
+                         "Start_Timestamp": 1000, "End_Timestamp": 1000 + ns})
+    rows.append({"Dispatch_Id": 3, "Kernel_Name": "k_adam<true>", "Counter_Name": "SQ_INSTS_MFMA",
+                 "Counter_Value": 0, "Start_Timestamp": 0, "End_Timestamp": 5})
+    with open(d / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0].keys()))
+        w.writeheader()
+        w.writerows(rows)
+    res = mc.summarise(mc._rows(str(d)))
+    assert len(res) == 1
+    r = res[0]
+    assert r["kernel"] == "k_gemm<64, 64, 16, 2, 2, false, false, 2, 0>" and r["dispatches"] == 2
+    assert abs(r["mfma_util"] - 0.5) < 1e-12 and abs(r["busy_cycles_per_mfma"] - 64.0) < 1e-9
+    assert abs(r["avg_us"] - 15.0) < 1e-12
+    assert abs(r["lds_conflict_per_active"] - 0.1) < 1e-12 and abs(r["lds_wait_share"] - 0.1) < 1e-12
+    out = tmp_path / "s.md"
+    mc.write_summary(str(out), res, "C2", "cmd")
+    assert "50.0%" in out.read_text()
