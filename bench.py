@@ -59,7 +59,7 @@ def build_workload(name: str, per_graph: bool = False):
     return pr, g, params
 
 
-def make_solver(pr, g, params, per_graph: bool = False):
+def make_solver(pr, g, params, per_graph: bool = False, edge_weight=None):
     from paper_2402_02190_amd import api
     from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
     dg = api.DeviceGraph.from_csr(g)
@@ -67,7 +67,7 @@ def make_solver(pr, g, params, per_graph: bool = False):
                      hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu,
                      gamma_start=pr.gamma_start, gamma_end=pr.gamma_end, T=pr.T, lr=pr.lr,
                      recompute=pr.recompute, per_graph_weights=per_graph)
-    sol = CPRASolver(dg, cfg, pr.lam)
+    sol = CPRASolver(dg, cfg, pr.lam, edge_weight=edge_weight)
     sol.load_params(params)
     return sol
 
@@ -119,7 +119,7 @@ def pmc_pass(sol, steps: int):
     log(f"[bench] pmc pass: calibration copy + {steps} steps done")
 
 
-def cpu_baseline(pr, g, params, seconds: float, per_graph: bool = False):
+def cpu_baseline(pr, g, params, seconds: float, per_graph: bool = False, edge_weight=None):
     """The FP64 oracle's training step timed on the host, on a bounded number of steps."""
     from oracle import gnn as ognn
     from oracle import train as otrain
@@ -131,7 +131,7 @@ def cpu_baseline(pr, g, params, seconds: float, per_graph: bool = False):
     p64 = ognn.to_f64(params)
     M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
     cfg = otrain.StepConfig(problem=pr.problem, lam=None if pr.lam is None else pr.lam.astype(np.float64),
-                            alpha=pr.alpha, nu=pr.nu, lr=pr.lr)
+                            alpha=pr.alpha, nu=pr.nu, lr=pr.lr, edge_weight=edge_weight)
     opt = otrain.AdamState(p64)
     times = []
     t_start = time.perf_counter()
@@ -245,6 +245,11 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--per-graph-weights", action="store_true",
                     help="batched workloads: one network per graph instead of one shared network")
+    ap.add_argument("--instances", default=None, choices=["uniform", "signed", "integer", "unit"],
+                    help="one instance per head: per-head edge weights of this kind on the "
+                         "workload's graph (seeded; see workloads.instance_edge_weights)")
+    ap.add_argument("--instance-drop", type=float, default=0.0,
+                    help="with --instances: fraction of (edge, head) pairs left out")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -268,7 +273,9 @@ def main():
         return
     label = args.workload + ("_pergraph" if args.per_graph_weights else "")
     if args.tuning_file is None and not args.no_autotune:
-        args.tuning_file = default_tuning_file(label)
+        args.tuning_file = default_tuning_file(label)  # the GEMMs do not depend on the instances
+    if args.instances:
+        label += "_instances"
     if args.gpus != 1:
         log("bench.py measures one GPU: the library runs one process on one GPU (a batch of graphs "
             "would shard at graph boundaries, one share per GPU). Run with --gpus 1.")
@@ -279,7 +286,11 @@ def main():
     from paper_2402_02190_amd import api
 
     pr, g, params = build_workload(args.workload, args.per_graph_weights)
-    sol = make_solver(pr, g, params, args.per_graph_weights)
+    W = None
+    if args.instances:
+        from workloads import instance_edge_weights
+        W = instance_edge_weights(g, pr.S, 2025, args.instances, args.instance_drop)
+    sol = make_solver(pr, g, params, args.per_graph_weights, W)
     torch.cuda.synchronize()
     log(f"[bench] params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
 
@@ -334,7 +345,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{pr.name}: {pr.description}"
-                               + ("; one network per graph" if args.per_graph_weights else ""),
+                               + ("; one network per graph" if args.per_graph_weights else "")
+                               + (f"; one instance per head ({args.instances} edge weights, "
+                                  f"{args.instance_drop:g} left out)" if args.instances else ""),
                    "n_nodes": g.n,
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
@@ -379,7 +392,8 @@ def main():
 
     if rank == 0 and not args.no_cpu_baseline:
         log(f"[bench] timing the FP64 oracle for up to {args.cpu_seconds:.0f}s ...")
-        result["cpu_baseline"] = cpu_baseline(pr, g, params, args.cpu_seconds, args.per_graph_weights)
+        result["cpu_baseline"] = cpu_baseline(pr, g, params, args.cpu_seconds, args.per_graph_weights,
+                                              W)
         log(f"[bench] cpu baseline: {result['cpu_baseline']}")
 
     sol.close()

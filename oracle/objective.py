@@ -96,9 +96,11 @@ def instance_weights(graph, edge_weight, S: int) -> np.ndarray:
     w = np.asarray(edge_weight, dtype=np.float64)
     if w.shape != (ci.size, S):
         raise ValueError("per-head edge weights must be [nnz, S]")
-    rows = np.repeat(np.arange(rp.size - 1, dtype=np.int64), np.diff(rp))
-    pos = {(int(i), int(j)): k for k, (i, j) in enumerate(zip(rows, ci))}
-    back = np.array([pos[(int(j), int(i))] for i, j in zip(rows, ci)], dtype=np.int64)
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    # entry (j, i) of every entry (i, j): the CSR keys i * n + j are sorted
+    keys = rows * n + ci
+    back = np.searchsorted(keys, ci * n + rows)
     if back.size and not np.array_equal(w, w[back]):
         raise ValueError("per-head edge weights must be symmetric")
     return w
