@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 6
+#define CPRA_ABI_VERSION 7
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -82,6 +82,10 @@ typedef struct {
   const float* weight;      /* device [nnz] A_ij, or NULL for A_ij = 1 */
   const float* inv_deg;     /* device [N] 1/|N(i)| (0 for isolated nodes), from cpra_csr_prepare */
   const float* wdeg;        /* device [N] sum_j A_ij, from cpra_csr_prepare */
+  const float* col_inv_deg; /* device [nnz] inv_deg[col_idx[e]] per CSR entry, from
+                             * cpra_csr_prepare_col, or NULL: the scale of M^T = A D^-1 read
+                             * in CSR order by the transposed aggregation instead of one
+                             * gather of inv_deg per neighbour (same values, same result) */
 } cpra_csr;
 
 /* Host-side validation of a CSR (host pointers).  Checks row_ptr[0] = 0,
@@ -97,6 +101,13 @@ cpra_status cpra_csr_validate_host(int32_t n_nodes, int64_t nnz, const int32_t* 
  * coefficient of the MaxCut objective.  Reads g->row_ptr and g->weight only
  * (g->inv_deg / g->wdeg may still be NULL).  Either output may be NULL. */
 cpra_status cpra_csr_prepare(const cpra_csr* g, float* inv_deg, float* wdeg, cpra_stream_t stream);
+
+/* Fills col_inv_deg[e] = g->inv_deg[g->col_idx[e]] for every CSR entry e: the
+ * factor D^-1 of M^T = A D^-1 (GNN appendix, mean aggregation, transposed for
+ * the backward pass) laid out per entry.  Needs g->inv_deg (cpra_csr_prepare);
+ * col_inv_deg [nnz] is caller-owned device memory.  CPRA_ERR_NULL when
+ * g->inv_deg or col_inv_deg is NULL and nnz > 0. */
+cpra_status cpra_csr_prepare_col(const cpra_csr* g, float* col_inv_deg, cpra_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Mean aggregation (GNN appendix: Aggregate step with the 1/|N(v)|

@@ -29,7 +29,8 @@ class CpraError(RuntimeError):
 class Csr(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_graphs", C.c_int32), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("graph_ptr", C.c_void_p),
-                ("weight", C.c_void_p), ("inv_deg", C.c_void_p), ("wdeg", C.c_void_p)]
+                ("weight", C.c_void_p), ("inv_deg", C.c_void_p), ("wdeg", C.c_void_p),
+                ("col_inv_deg", C.c_void_p)]
 
 
 class LossCfg(C.Structure):
@@ -79,6 +80,7 @@ PROTOTYPES = {
     "cpra_last_error_message": (C.c_char_p, []),
     "cpra_csr_validate_host": (None, [I32, I64, P, P, P]),
     "cpra_csr_prepare": (None, [PCsr, P, P, P]),
+    "cpra_csr_prepare_col": (None, [PCsr, P, P]),
     "cpra_aggregate_mean": (None, [PCsr, I32, I32, P, I64, P, I64, P, I64, P, I32, P, I64, P]),
     "cpra_gemm_workspace_bytes": (SZ, [I32, I32, I32, I32, I32]),
     "cpra_gemm": (None, [I32, I32, I32, I32, I32, P, I64, P, I64, F32, P, I64, P, I32, P, SZ, P]),

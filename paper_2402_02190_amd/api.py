@@ -64,6 +64,10 @@ class DeviceGraph:
         csr_prepare(self, self.inv_deg, self.wdeg)
         self.csr.inv_deg = _ptr(self.inv_deg)
         self.csr.wdeg = _ptr(self.wdeg)
+        # the column scale of M^T per CSR entry, read in order by the transposed aggregation
+        self.col_inv_deg = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=device)
+        csr_prepare_col(self, self.col_inv_deg)
+        self.csr.col_inv_deg = _ptr(self.col_inv_deg)
 
     @classmethod
     def from_csr(cls, g, device="cuda", validate=True):
@@ -94,6 +98,10 @@ def csr_validate_host(row_ptr, col_idx, weight=None) -> None:
 
 def csr_prepare(g, inv_deg: Optional[torch.Tensor], wdeg: Optional[torch.Tensor], stream=None):
     call("cpra_csr_prepare", _csr(g), _ptr(inv_deg), _ptr(wdeg), _stream(stream))
+
+
+def csr_prepare_col(g, col_inv_deg: torch.Tensor, stream=None):
+    call("cpra_csr_prepare_col", _csr(g), _ptr(col_inv_deg), _stream(stream))
 
 
 def aggregate_mean(g, X: torch.Tensor, Y: torch.Tensor, transpose: bool = False,

@@ -65,6 +65,7 @@ struct AggArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
   const float* inv_deg;
+  const float* col_inv_deg;  // inv_deg of each entry's column, or null (gathered instead)
   const float* X;
   int64_t ldx;
   float* Y;
@@ -119,7 +120,9 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
 #pragma unroll
     for (int i = 0; i < CH; ++i) j[i] = a.col_idx[min(k + i, end - 1)];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) s[i] = TRANS ? a.inv_deg[j[i]] : 1.f;
+    for (int i = 0; i < CH; ++i)
+      s[i] = !TRANS ? 1.f
+                    : a.col_inv_deg ? a.col_inv_deg[min(k + i, end - 1)] : a.inv_deg[j[i]];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int u = c * lpr + cl;
@@ -177,7 +180,8 @@ cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, 
   const double nw = (double)a.n * a.width * 4.0;
   const double bytes = nw * (2.0 + (a.add ? 1.0 : 0.0) + (a.add2 ? 1.0 : 0.0) +
                              (a.mask ? 1.0 : 0.0) + (a.sig_out ? 1.0 : 0.0)) +
-                       4.0 * (double)nnz + 8.0 * (double)a.n + 4.0;
+                       4.0 * (double)nnz * (TRANS && a.col_inv_deg ? 2.0 : 1.0) +
+                       8.0 * (double)a.n + 4.0;
   ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes);
   switch (nc) {
 #define CPRA_AGG_CASE(NCV)                                                                    \
@@ -226,7 +230,7 @@ cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float*
   while (nc < need) nc <<= 1;
   if (nc > 16) CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate: width %d exceeds 4096", width);
   AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
-            X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2};
+            g->col_inv_deg, X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2};
   int rows_per_block = 4 * (64 / lpr);
   int blocks = (int)ceil_div(g->n_nodes, rows_per_block);
   if (transpose) {

@@ -23,6 +23,13 @@ __global__ void k_csr_prepare(int n, const int32_t* __restrict__ row_ptr,
   }
 }
 
+// col_inv_deg[e] = inv_deg[col_idx[e]]: the column scale of M^T = A D^-1 per CSR entry.
+__global__ void k_csr_prepare_col(int64_t nnz, const int32_t* __restrict__ col_idx,
+                                  const float* __restrict__ inv_deg, float* __restrict__ col_inv_deg) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) col_inv_deg[e] = inv_deg[col_idx[e]];
+}
+
 // Exclusive scan of ceil(n_g / R) over graphs by one block, in chunks of blockDim.
 __global__ void k_item_ptr(int n_graphs, const int32_t* __restrict__ graph_ptr, int R,
                            int32_t* __restrict__ item_ptr) {
@@ -170,6 +177,17 @@ cpra_status cpra_csr_prepare(const cpra_csr* g, float* inv_deg, float* wdeg, cpr
   hipLaunchKernelGGL(cpra::k_csr_prepare, dim3(cpra::ceil_div(g->n_nodes, 256)), dim3(256), 0,
                      cpra::as_stream(stream), g->n_nodes, g->row_ptr, g->weight, inv_deg, wdeg);
   CPRA_CHECK_LAUNCH("csr_prepare");
+  return CPRA_OK;
+}
+
+cpra_status cpra_csr_prepare_col(const cpra_csr* g, float* col_inv_deg, cpra_stream_t stream) {
+  CPRA_CHECK(cpra::check_csr(g, "csr_prepare_col", false, false));
+  if (g->nnz == 0) return CPRA_OK;
+  if (g->inv_deg == nullptr || col_inv_deg == nullptr)
+    CPRA_FAIL(CPRA_ERR_NULL, "csr_prepare_col: g->inv_deg or col_inv_deg is NULL");
+  hipLaunchKernelGGL(cpra::k_csr_prepare_col, dim3((unsigned)cpra::ceil_div(g->nnz, 256)), dim3(256),
+                     0, cpra::as_stream(stream), g->nnz, g->col_idx, g->inv_deg, col_inv_deg);
+  CPRA_CHECK_LAUNCH("csr_prepare_col");
   return CPRA_OK;
 }
 

@@ -136,6 +136,7 @@ struct AggBfArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
   const float* inv_deg;
+  const float* col_inv_deg;  // inv_deg of each entry's column, or null (gathered instead)
   const void* X;  // bf16 rows (forward) or float rows (transposed)
   int64_t ldx;
   uint16_t* Y;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_agg_bf16(AggBfArgs a) {
   const int beg = a.row_ptr[row], end = a.row_ptr[row + 1];
   for (int k = beg; k < end; ++k) {
     const int j = a.col_idx[k];
-    const float s = TRANS ? a.inv_deg[j] : 1.0f;
+    const float s = !TRANS ? 1.0f : a.col_inv_deg ? a.col_inv_deg[k] : a.inv_deg[j];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int u = c * lpr + cl;
@@ -492,8 +493,8 @@ cpra_status agg_bf16(const cpra_csr* g, bool trans, int width, const void* X, in
   while (lpr < units) lpr <<= 1;
   int lpr_log2 = 0;
   while ((1 << lpr_log2) < lpr) ++lpr_log2;
-  AggBfArgs a{g->n_nodes, units, lpr_log2, g->row_ptr, g->col_idx, g->inv_deg, X, ldx, Y, ldy,
-              add, ld_add, mask, ld_mask};
+  AggBfArgs a{g->n_nodes, units, lpr_log2, g->row_ptr, g->col_idx, g->inv_deg, g->col_inv_deg,
+              X, ldx, Y, ldy, add, ld_add, mask, ld_mask};
   const int rows_per_block = 4 * (64 >> lpr_log2);
   const int blocks = (int)ceil_div(g->n_nodes, rows_per_block);
   const double in_b = trans ? 4.0 : 2.0;

@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = _lib.lib()
-    assert lib.cpra_abi_version() == 6
+    assert lib.cpra_abi_version() == 7
     for code, name in _lib.STATUS.items():
         assert lib.cpra_status_string(code).decode() == name
 
@@ -57,6 +57,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(cpra_csr, inv_deg), offsetof(cpra_loss_cfg, lambda),
          offsetof(cpra_loss_cfg, step_counter), offsetof(cpra_loss_cfg, T),
          offsetof(cpra_step_cfg, adam), offsetof(cpra_loss_cfg, edge_weight));
+  printf("%zu\\n", offsetof(cpra_csr, col_inv_deg));
   return 0;
 }
 """)
@@ -71,6 +72,7 @@ int main(void) {
     assert offs == [_lib.Csr.inv_deg.offset, _lib.LossCfg.lambda_.offset,
                     _lib.LossCfg.step_counter.offset, _lib.LossCfg.T.offset, _lib.StepCfg.adam.offset,
                     _lib.LossCfg.edge_weight.offset]
+    assert int(lines[2]) == _lib.Csr.col_inv_deg.offset
 
 
 def _validate(rp, ci, w=None):

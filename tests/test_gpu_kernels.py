@@ -438,3 +438,32 @@ def test_pairwise_hamming_bit_exact(N, S):
     a.pairwise_hamming(Xd, None, hist2, nu2)
     torch.cuda.synchronize()
     assert torch.equal(hist2, hist) and torch.equal(nu2, nu)
+
+
+@pytest.mark.parametrize("gname", ["er_sparse_300", "rrg20_500", "batch"])
+@pytest.mark.parametrize("width", [1, 6, 64, 300])
+def test_transposed_aggregation_with_per_entry_scale_is_bit_identical(gname, width):
+    """cpra_csr_prepare_col gives inv_deg[col_idx[e]] per entry, and the transposed
+    aggregation reading it in CSR order equals the one gathering inv_deg per
+    neighbour, bit for bit (the same products in the same order)."""
+    a = api()
+    g = GRAPHS[gname]()
+    dg = a.DeviceGraph.from_csr(g)
+    inv = dg.inv_deg[: g.n].cpu().numpy()
+    col = dg.col_inv_deg[: g.nnz].cpu().numpy()
+    assert np.array_equal(col, inv[g.col_idx])
+    X = to_dev(np.random.default_rng(width).standard_normal((g.n, width)).astype(np.float32))
+    Y1 = torch.empty_like(X)
+    Y2 = torch.empty_like(X)
+    a.aggregate_mean(dg, X, Y1, transpose=True)
+    saved = dg.csr.col_inv_deg
+    dg.csr.col_inv_deg = None  # the gathering form
+    try:
+        a.aggregate_mean(dg, X, Y2, transpose=True)
+    finally:
+        dg.csr.col_inv_deg = saved
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    ref = A @ (inv[:, None].astype(np.float64) * X.cpu().double().numpy())
+    assert_close_array(Y1.cpu().numpy(), ref, 1e-6, "M^T X")
