@@ -1,5 +1,6 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times
-(autotuned GEMM plans, side-stream overlap, the same presets), and the
+(autotuned GEMM plans, side-stream overlap, the same presets; also with one
+instance per head, as ``bench.py --instances`` runs them), and the
 hand-written backward against finite differences on a 1,000-node subgraph of
 the 100,000-node workload.
 
@@ -25,26 +26,33 @@ def _gpu():
     need_gpu()
 
 
-def _solver_for(pr, g, seed):
+def _solver_for(pr, g, seed, edge_weight=None):
     from paper_2402_02190_amd import api
     from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
     dg = api.DeviceGraph.from_csr(g)
     cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
                      hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu, gamma_start=pr.gamma_start,
                      gamma_end=pr.gamma_end, T=pr.T, lr=pr.lr, recompute=pr.recompute)
-    sol = CPRASolver(dg, cfg, pr.lam)
+    sol = CPRASolver(dg, cfg, pr.lam, edge_weight=edge_weight)
     params = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=seed)
     sol.load_params(params)
     return sol
 
 
-@pytest.mark.parametrize("preset", ["C2", "C4", "C3s"])
-def test_full_size_step_teacher_forced(preset):
+FULL_CASES = [("C2", None, 0.0), ("C4", None, 0.0), ("C3s", None, 0.0),
+              ("C2", "integer", 0.0), ("C4", "signed", 0.2)]  # the last two: one instance per head
+
+
+@pytest.mark.parametrize("preset,instances,drop", FULL_CASES,
+                         ids=[f"{p}{'_' + i if i else ''}" for p, i, _ in FULL_CASES])
+def test_full_size_step_teacher_forced(preset, instances, drop):
     from paper_2402_02190_amd.solver import gamma_schedule
+    from workloads import instance_edge_weights
     pr = get_preset(preset)
     g = pr.graph()
-    say(f"full-size {preset}: n={g.n} edges={g.n_edges} graphs={g.n_graphs}")
-    sol = _solver_for(pr, g, seed=7)
+    say(f"full-size {preset}: n={g.n} edges={g.n_edges} graphs={g.n_graphs} instances={instances}")
+    W = instance_edge_weights(g, pr.S, 2025, instances, drop) if instances else None
+    sol = _solver_for(pr, g, seed=7, edge_weight=W)
     sol.autotune()  # step 0, with the bench's tuned GEMM plans from here on
     torch.cuda.synchronize()
     t = sol.t
@@ -55,7 +63,7 @@ def test_full_size_step_teacher_forced(preset):
     gamma = gamma_schedule(t, pr.T, pr.gamma_start, pr.gamma_end)
     M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
     ocfg = otrain.StepConfig(problem=pr.problem, lam=None if pr.lam is None else pr.lam.astype(np.float64),
-                             alpha=pr.alpha, nu=pr.nu, lr=pr.lr)
+                             alpha=pr.alpha, nu=pr.nu, lr=pr.lr, edge_weight=W)
     # The ReLU derivative is a discrete decision: take it where the FP32 forward took it,
     # after checking that every disagreement with the FP64 forward sits at Y ~ 0.
     active = sol.relu_active()
