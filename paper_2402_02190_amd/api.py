@@ -203,11 +203,16 @@ def make_loss_cfg(problem: int, S: int, lam: Optional[torch.Tensor], alpha: int 
                   edge_weight: Optional[torch.Tensor] = None) -> LossCfg:
     """node_weight: optional MIS node weights, float32 [N] or [N, S] on the device;
     edge_weight: optional per-head edge weights, float32 [nnz, S] (one instance per
-    head; symmetric).  The caller keeps the tensors alive while the config is used."""
+    head; symmetric).  The returned config keeps references to the tensors whose
+    addresses it holds; a StepCfg built from it copies the struct, so keep this
+    object (or the tensors) while the StepCfg is used."""
     nw, ld = _node_weight_args(node_weight)
     ew, lde = _edge_weight_args(edge_weight)
-    return LossCfg(problem, S, alpha, std_ddof, gamma, nu, _ptr(lam), _ptr(step_counter),
-                   gamma_start, gamma_end, T, nw, ld, ew, lde)
+    cfg = LossCfg(problem, S, alpha, std_ddof, gamma, nu, _ptr(lam), _ptr(step_counter),
+                  gamma_start, gamma_end, T, nw, ld, ew, lde)
+    # the struct holds raw addresses: keep the tensors alive as long as this object
+    cfg._tensors = (lam, step_counter, node_weight, edge_weight)
+    return cfg
 
 
 def loss_workspace_bytes(g, cfg: LossCfg) -> int:
@@ -240,9 +245,11 @@ def make_model_cfg(layer_kind: int, n_layers: int, in_dim: int, hidden: int, S: 
         if z_offset.dtype != torch.float32 or not z_offset.is_contiguous() or z_offset.dim() != 2 \
                 or z_offset.shape[1] != S:
             raise ValueError("z_offset must be a contiguous float32 [N, S] tensor")
-    return ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute),
-                    None if z_offset is None else z_offset.data_ptr(), int(train_from_layer),
-                    int(reuse_frozen_prefix), int(weight_groups))
+    cfg = ModelCfg(layer_kind, n_layers, in_dim, hidden, S, int(recompute),
+                   None if z_offset is None else z_offset.data_ptr(), int(train_from_layer),
+                   int(reuse_frozen_prefix), int(weight_groups))
+    cfg._tensors = (z_offset,)  # kept alive with the struct that holds its address
+    return cfg
 
 
 def model_param_count(cfg: ModelCfg, n_nodes: int) -> int:

@@ -193,3 +193,20 @@ def test_workspace_queries_are_host_only():
     assert api.model_workspace_bytes(csr, mcfg) > 0
     assert api.gemm_workspace_bytes(1, 0, 200, 256, 10000) > 0  # weight-gradient shape splits K
     assert api.gemm_workspace_bytes(0, 1, 64, 64, 8) == 0       # one short K step: never split
+
+
+def test_configs_keep_the_tensors_whose_addresses_they_hold():
+    """A tensor passed straight into a config builder lives as long as the config."""
+    import gc
+    import weakref
+    import torch
+    from paper_2402_02190_amd import api
+    lam = torch.linspace(0.5, 2.0, 4)
+    ref = weakref.ref(lam)
+    cfg = api.make_loss_cfg(api.MIS, 4, lam)
+    del lam
+    gc.collect()
+    assert ref() is not None and cfg.lambda_ == ref().data_ptr()
+    del cfg
+    gc.collect()
+    assert ref() is None
