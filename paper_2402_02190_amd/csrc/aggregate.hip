@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   const int sub = lane >> a.lpr_log2;
   const int cl = lane & (lpr - 1);
   const int rpw = 64 >> a.lpr_log2;
-  const int row = (blockIdx.x * 4 + wave) * rpw + sub;
+  const int row = (xcd_unit(blockIdx.x, gridDim.x) * 4 + wave) * rpw + sub;
   if (row >= a.n) return;
   const int units = a.width / VEC;
 
@@ -232,7 +232,7 @@ cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float*
   AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
             g->col_inv_deg, X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2};
   int rows_per_block = 4 * (64 / lpr);
-  int blocks = (int)ceil_div(g->n_nodes, rows_per_block);
+  int blocks = (int)xcd_grid(ceil_div(g->n_nodes, rows_per_block));
   if (transpose) {
     if (vec == 4) return launch_nc<4, true>(a, nc, blocks, stream, g->nnz);
     if (vec == 2) return launch_nc<2, true>(a, nc, blocks, stream, g->nnz);

@@ -69,6 +69,15 @@ cpra_status launch_item_ptr(const cpra_csr* g, int rows_per_item, int32_t* item_
 
 // Device helper: the graph and row range of item b.  Returns false when b is
 // past the last item.
+// XCD-aware block order.  The hardware deals consecutive block ids round-robin
+// to the 8 XCDs, each with its own L2.  With a grid of 8 * per blocks, block b
+// takes work unit (b % 8) * per + b / 8, a bijection on [0, 8 * per): each XCD
+// then works through one contiguous eighth of the units, so the rows of one
+// graph of a batch (and their neighbours' rows) are gathered into one L2 instead
+// of eight.
+__device__ inline int xcd_unit(int b, int grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
+inline int64_t xcd_grid(int64_t units) { return (units + 7) / 8 * 8; }
+
 __device__ inline bool item_rows(int b, int n_graphs, int n_nodes, const int32_t* graph_ptr,
                                  const int32_t* item_ptr, int R, int* g_out, int* r0, int* r1) {
   if (graph_ptr == nullptr) {

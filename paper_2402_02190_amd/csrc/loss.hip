@@ -66,7 +66,8 @@ __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
 template <int NC, bool PH>
 __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   int g, r0, r1;
-  if (!item_rows(blockIdx.x, a.n_graphs, a.n, a.graph_ptr, a.item_ptr, a.R, &g, &r0, &r1)) return;
+  const int item = xcd_unit(blockIdx.x, gridDim.x);
+  if (!item_rows(item, a.n_graphs, a.n, a.graph_ptr, a.item_ptr, a.R, &g, &r0, &r1)) return;
 
   float gamma = a.gamma;
   if (a.step_counter) {
@@ -276,13 +277,13 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   for (int s = threadIdx.x; s < slots; s += 256) {
     if (s < S) {
       const float v = ((sh_head[0][s] + sh_head[1][s]) + sh_head[2][s]) + sh_head[3][s];
-      a.part[(int64_t)s * a.items_cap + blockIdx.x] = v;
+      a.part[(int64_t)s * a.items_cap + item] = v;
     }
   }
   if (threadIdx.x == 0) {
-    a.part[(int64_t)S * a.items_cap + blockIdx.x] =
+    a.part[(int64_t)S * a.items_cap + item] =
         ((sh_scal[0][0] + sh_scal[1][0]) + sh_scal[2][0]) + sh_scal[3][0];
-    a.part[(int64_t)(S + 1) * a.items_cap + blockIdx.x] =
+    a.part[(int64_t)(S + 1) * a.items_cap + item] =
         ((sh_scal[0][1] + sh_scal[1][1]) + sh_scal[2][1]) + sh_scal[3][1];
   }
 }
@@ -417,7 +418,7 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.edge_w = cfg->edge_weight;
   a.ld_ew = cfg->ld_edge_weight;
   const bool ph = cfg->edge_weight != nullptr;
-  const int blocks = (int)G.items_cap;
+  const int blocks = (int)xcd_grid(G.items_cap);
   // compulsory bytes: Z and P read once, dZ written, CSR (+weights), wdeg, partials
   const double ns4 = 4.0 * (double)g->n_nodes * S;
   const double loss_bytes = ns4 * (dZ ? 3.0 : 2.0) +
