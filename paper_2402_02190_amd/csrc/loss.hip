@@ -63,7 +63,31 @@ __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
   return v;
 }
 
-template <int NC, bool PH>
+// Per-lane vectors of VEC consecutive heads (float4 when VEC = 4).
+template <int VEC>
+struct HV {
+  float v[VEC];
+  __device__ inline void load(const float* p) {
+    if constexpr (VEC == 4) {
+      const float4 x = *reinterpret_cast<const float4*>(p);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+      v[0] = *p;
+    }
+  }
+  __device__ inline void store(float* p) const {
+    if constexpr (VEC == 4) *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    else *p = v[0];
+  }
+  __device__ inline void zero() {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = 0.0f;
+  }
+};
+
+// Lane layout: a wavefront holds 64/LPR nodes; lane cl of a node owns NC units
+// of VEC consecutive heads, unit c covering heads (c * LPR + cl) * VEC + e.
+template <int NC, int VEC, bool PH>
 __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   int g, r0, r1;
   const int item = xcd_unit(blockIdx.x, gridDim.x);
@@ -89,64 +113,75 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   const bool diverse = a.nu != 0.0f && S > 1;          // gradient of Psi needed
   const bool stats = S > 1 && (diverse || a.want_psi);  // Psi itself needed
 
-  float lam_h[NC];
+  int h0[NC];      // first head of each unit
+  bool uok[NC];    // unit inside [0, S) (S is a multiple of VEC)
+  HV<VEC> lam_h[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int s = c * lpr + cl;
-    lam_h[c] = (mis && s < S) ? a.lambda[s] : 0.0f;
+    h0[c] = (c * lpr + cl) * VEC;
+    uok[c] = h0[c] < S;
+    if (mis && uok[c]) lam_h[c].load(a.lambda + h0[c]); else lam_h[c].zero();
   }
 
-  float hl[NC];
+  HV<VEC> hl[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) hl[c] = 0.0f;
+  for (int c = 0; c < NC; ++c) hl[c].zero();
   float ent = 0.0f, psi = 0.0f;
 
   const int rows_per_iter = 4 * rpw;
   for (int base = r0; base < r1; base += rows_per_iter) {
     const int row = base + wave * rpw + sub;
     const bool active = row < r1;
-    float z[NC], ap[NC], wdh[NC];  // wdh: per-head weighted degree (PH)
+    HV<VEC> z[NC], ap[NC], wdh[NC];  // wdh: per-head weighted degree (PH)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int s = c * lpr + cl;
-      z[c] = (active && s < S) ? a.Z[(int64_t)row * a.ldz + s] : 0.0f;
-      ap[c] = 0.0f;
-      wdh[c] = 0.0f;
+      if (active && uok[c]) z[c].load(a.Z + (int64_t)row * a.ldz + h0[c]); else z[c].zero();
+      ap[c].zero();
+      wdh[c].zero();
     }
     if (active) {
       // Neighbours in full chunks of 4 (index and weight loads, then the four
       // gathers, then the adds in CSR order), and the remaining 1-3 as one
-      // predicated chunk, so that the tail costs one round trip, not one each.
+      // padded chunk, so that the tail costs one round trip, not one each.
       const int beg = a.row_ptr[row], end = a.row_ptr[row + 1];
       int k = beg;
       for (; k + 4 <= end; k += 4) {
         const int j0 = a.col_idx[k], j1 = a.col_idx[k + 1], j2 = a.col_idx[k + 2], j3 = a.col_idx[k + 3];
         float w0 = 1.f, w1 = 1.f, w2 = 1.f, w3 = 1.f;
-        if (a.weight) { w0 = a.weight[k]; w1 = a.weight[k + 1]; w2 = a.weight[k + 2]; w3 = a.weight[k + 3]; }
+        if (!PH && a.weight) { w0 = a.weight[k]; w1 = a.weight[k + 1]; w2 = a.weight[k + 2]; w3 = a.weight[k + 3]; }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const int s = c * lpr + cl;
-          if (s < S) {
-            const float p0 = a.P[(int64_t)j0 * a.ldp + s];
-            const float p1 = a.P[(int64_t)j1 * a.ldp + s];
-            const float p2 = a.P[(int64_t)j2 * a.ldp + s];
-            const float p3 = a.P[(int64_t)j3 * a.ldp + s];
-            if constexpr (PH) {
-              const float* e = a.edge_w + (int64_t)k * a.ld_ew + s;
-              const float v0 = e[0], v1 = e[a.ld_ew], v2 = e[2 * a.ld_ew], v3 = e[3 * a.ld_ew];
-              ap[c] += v0 * p0;
-              ap[c] += v1 * p1;
-              ap[c] += v2 * p2;
-              ap[c] += v3 * p3;
-              wdh[c] += v0;
-              wdh[c] += v1;
-              wdh[c] += v2;
-              wdh[c] += v3;
-            } else {
-              ap[c] += w0 * p0;
-              ap[c] += w1 * p1;
-              ap[c] += w2 * p2;
-              ap[c] += w3 * p3;
+          if (!uok[c]) continue;
+          HV<VEC> p0, p1, p2, p3;
+          p0.load(a.P + (int64_t)j0 * a.ldp + h0[c]);
+          p1.load(a.P + (int64_t)j1 * a.ldp + h0[c]);
+          p2.load(a.P + (int64_t)j2 * a.ldp + h0[c]);
+          p3.load(a.P + (int64_t)j3 * a.ldp + h0[c]);
+          if constexpr (PH) {
+            HV<VEC> v0, v1, v2, v3;
+            const float* e = a.edge_w + (int64_t)k * a.ld_ew + h0[c];
+            v0.load(e);
+            v1.load(e + a.ld_ew);
+            v2.load(e + 2 * a.ld_ew);
+            v3.load(e + 3 * a.ld_ew);
+#pragma unroll
+            for (int x = 0; x < VEC; ++x) {
+              ap[c].v[x] += v0.v[x] * p0.v[x];
+              ap[c].v[x] += v1.v[x] * p1.v[x];
+              ap[c].v[x] += v2.v[x] * p2.v[x];
+              ap[c].v[x] += v3.v[x] * p3.v[x];
+              wdh[c].v[x] += v0.v[x];
+              wdh[c].v[x] += v1.v[x];
+              wdh[c].v[x] += v2.v[x];
+              wdh[c].v[x] += v3.v[x];
+            }
+          } else {
+#pragma unroll
+            for (int x = 0; x < VEC; ++x) {
+              ap[c].v[x] += w0 * p0.v[x];
+              ap[c].v[x] += w1 * p1.v[x];
+              ap[c].v[x] += w2 * p2.v[x];
+              ap[c].v[x] += w3 * p3.v[x];
             }
           }
         }
@@ -154,38 +189,44 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
       if (k < end) {  // 1-3 left
         // entries past the end re-read the row's last neighbour (and add 0)
         const int n_left = end - k;
-        const int j0 = a.col_idx[k];
-        const int j1 = a.col_idx[min(k + 1, end - 1)];
-        const int j2 = a.col_idx[min(k + 2, end - 1)];
+        const int k1 = min(k + 1, end - 1), k2 = min(k + 2, end - 1);
+        const int j0 = a.col_idx[k], j1 = a.col_idx[k1], j2 = a.col_idx[k2];
         float w0 = 1.f, w1 = 1.f, w2 = 1.f;
-        if (a.weight) {
+        if (!PH && a.weight) {
           w0 = a.weight[k];
-          w1 = a.weight[min(k + 1, end - 1)];
-          w2 = a.weight[min(k + 2, end - 1)];
+          w1 = a.weight[k1];
+          w2 = a.weight[k2];
         }
+        w1 = n_left > 1 ? w1 : 0.f;  // padded entries add an exact zero (by a select, no branch)
+        w2 = n_left > 2 ? w2 : 0.f;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const int s = c * lpr + cl;
-          if (s < S) {
-            const float p0 = a.P[(int64_t)j0 * a.ldp + s];
-            const float p1 = a.P[(int64_t)j1 * a.ldp + s];
-            const float p2 = a.P[(int64_t)j2 * a.ldp + s];
-            // padded entries add an exact zero (weight 0 by a select, no branch)
-            if constexpr (PH) {
-              const float* e = a.edge_w + s;
-              const float v0 = e[(int64_t)k * a.ld_ew];
-              const float v1 = n_left > 1 ? e[(int64_t)min(k + 1, end - 1) * a.ld_ew] : 0.f;
-              const float v2 = n_left > 2 ? e[(int64_t)min(k + 2, end - 1) * a.ld_ew] : 0.f;
-              ap[c] += v0 * p0;
-              ap[c] += v1 * p1;
-              ap[c] += v2 * p2;
-              wdh[c] += v0;
-              wdh[c] += v1;
-              wdh[c] += v2;
-            } else {
-              ap[c] += w0 * p0;
-              ap[c] += (n_left > 1 ? w1 : 0.f) * p1;
-              ap[c] += (n_left > 2 ? w2 : 0.f) * p2;
+          if (!uok[c]) continue;
+          HV<VEC> p0, p1, p2;
+          p0.load(a.P + (int64_t)j0 * a.ldp + h0[c]);
+          p1.load(a.P + (int64_t)j1 * a.ldp + h0[c]);
+          p2.load(a.P + (int64_t)j2 * a.ldp + h0[c]);
+          if constexpr (PH) {
+            HV<VEC> v0, v1, v2;
+            v0.load(a.edge_w + (int64_t)k * a.ld_ew + h0[c]);
+            v1.load(a.edge_w + (int64_t)k1 * a.ld_ew + h0[c]);
+            v2.load(a.edge_w + (int64_t)k2 * a.ld_ew + h0[c]);
+#pragma unroll
+            for (int x = 0; x < VEC; ++x) {
+              const float u1 = n_left > 1 ? v1.v[x] : 0.f, u2 = n_left > 2 ? v2.v[x] : 0.f;
+              ap[c].v[x] += v0.v[x] * p0.v[x];
+              ap[c].v[x] += u1 * p1.v[x];
+              ap[c].v[x] += u2 * p2.v[x];
+              wdh[c].v[x] += v0.v[x];
+              wdh[c].v[x] += u1;
+              wdh[c].v[x] += u2;
+            }
+          } else {
+#pragma unroll
+            for (int x = 0; x < VEC; ++x) {
+              ap[c].v[x] += w0 * p0.v[x];
+              ap[c].v[x] += w1 * p1.v[x];
+              ap[c].v[x] += w2 * p2.v[x];
             }
           }
         }
@@ -193,14 +234,17 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
     }
     const float wd = (!PH && active && !mis) ? a.wdeg[row] : 0.0f;
 
-    float p[NC], q[NC];
+    HV<VEC> p[NC], q[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const float e = expf(-fabsf(z[c]));
-      const float r = 1.0f / (1.0f + e);
-      p[c] = z[c] >= 0.0f ? r : e * r;
-      q[c] = z[c] >= 0.0f ? e * r : r;
-    }
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int x = 0; x < VEC; ++x) {
+        const float zz = z[c].v[x];
+        const float e = expf(-fabsf(zz));
+        const float r = 1.0f / (1.0f + e);
+        p[c].v[x] = zz >= 0.0f ? r : e * r;
+        q[c].v[x] = zz >= 0.0f ? e * r : r;
+      }
 
     // Diversity statistics of the node across its heads (two passes).
     float mu = 0.0f, sig = 0.0f, inv_dev_scale = 0.0f;
@@ -208,16 +252,20 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
       float sp = 0.0f;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        if (c * lpr + cl < S) sp += p[c];
+        if (uok[c])
+#pragma unroll
+          for (int x = 0; x < VEC; ++x) sp += p[c].v[x];
       sp = wave_sum_xor(sp, 1, lpr);
       mu = sp / (float)S;
       float sd = 0.0f;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        if (c * lpr + cl < S) {
-          const float d = p[c] - mu;
-          sd += d * d;
-        }
+        if (uok[c])
+#pragma unroll
+          for (int x = 0; x < VEC; ++x) {
+            const float d = p[c].v[x] - mu;
+            sd += d * d;
+          }
       sd = wave_sum_xor(sd, 1, lpr);
       sig = sqrtf(sd / (float)(S - a.ddof));
       inv_dev_scale = sig > 0.0f ? -(float)S / ((float)(S - a.ddof) * sig) : 0.0f;
@@ -226,44 +274,59 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
 
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int s = c * lpr + cl;
-      if (!active || s >= S) continue;
-      const float t = p[c] - q[c];
-      const float t2 = t * t;
-      float series = 1.0f, tp = 1.0f;
-      for (int kk = 1; kk < half_alpha; ++kk) {
-        tp *= t2;
-        series += tp;
-      }
-      const float phi = 4.0f * p[c] * q[c] * series;
-      const float t_am1 = t * tp;  // t^(alpha-1)
-      float l, gr;
+      if (!active || !uok[c]) continue;
+      HV<VEC> u, dz;
       if (mis) {
-        const float u = a.node_w ? -a.node_w[a.ld_nw ? (int64_t)row * a.ld_nw + s : (int64_t)row]
-                                 : -1.0f;
-        l = p[c] * (u + 0.5f * lam_h[c] * ap[c]);
-        gr = u + lam_h[c] * ap[c];
-      } else {
-        const float wdc = PH ? wdh[c] : wd;
-        l = p[c] * (ap[c] - wdc);
-        gr = 2.0f * ap[c] - wdc;
+        if (a.node_w && a.ld_nw) {
+          u.load(a.node_w + (int64_t)row * a.ld_nw + h0[c]);
+        } else {
+          const float w = a.node_w ? a.node_w[row] : 1.0f;
+#pragma unroll
+          for (int x = 0; x < VEC; ++x) u.v[x] = w;
+        }
       }
-      gr -= two_alpha_gamma * t_am1;
-      if (diverse) gr += a.nu * inv_dev_scale * (p[c] - mu);
-      hl[c] += l;
-      ent += phi;
-      if (a.dZ) a.dZ[(int64_t)row * a.lddz + s] = gr * p[c] * q[c];
+#pragma unroll
+      for (int x = 0; x < VEC; ++x) {
+        const float pp = p[c].v[x], qq = q[c].v[x], aa = ap[c].v[x];
+        const float t = pp - qq;
+        const float t2 = t * t;
+        float series = 1.0f, tp = 1.0f;
+        for (int kk = 1; kk < half_alpha; ++kk) {
+          tp *= t2;
+          series += tp;
+        }
+        const float phi = 4.0f * pp * qq * series;
+        const float t_am1 = t * tp;  // t^(alpha-1)
+        float l, gr;
+        if (mis) {
+          const float un = -u.v[x];
+          l = pp * (un + 0.5f * lam_h[c].v[x] * aa);
+          gr = un + lam_h[c].v[x] * aa;
+        } else {
+          const float wdc = PH ? wdh[c].v[x] : wd;
+          l = pp * (aa - wdc);
+          gr = 2.0f * aa - wdc;
+        }
+        gr -= two_alpha_gamma * t_am1;
+        if (diverse) gr += a.nu * inv_dev_scale * (pp - mu);
+        hl[c].v[x] += l;
+        ent += phi;
+        dz.v[x] = gr * pp * qq;
+      }
+      if (a.dZ) dz.store(a.dZ + (int64_t)row * a.lddz + h0[c]);
     }
   }
 
   // ---- block reduction into this item's partial column entries ----------
-  __shared__ float sh_head[4][NC * 64];
+  __shared__ float sh_head[4][NC * 64 * VEC];
   __shared__ float sh_scal[4][2];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const float v = wave_sum_xor(hl[c], lpr, 64);
-    if (sub == 0) sh_head[wave][c * lpr + cl] = v;
-  }
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int x = 0; x < VEC; ++x) {
+      const float v = wave_sum_xor(hl[c].v[x], lpr, 64);
+      if (sub == 0) sh_head[wave][h0[c] + x] = v;
+    }
   {
     const float e = wave_sum_xor(ent, 1, 64);
     const float ps = wave_sum_xor(psi, 1, 64);
@@ -273,7 +336,7 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
     }
   }
   __syncthreads();
-  const int slots = NC * lpr;
+  const int slots = NC * lpr * VEC;
   for (int s = threadIdx.x; s < slots; s += 256) {
     if (s < S) {
       const float v = ((sh_head[0][s] + sh_head[1][s]) + sh_head[2][s]) + sh_head[3][s];
@@ -288,28 +351,46 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   }
 }
 
+// Lanes per node (LPR), units per lane (NC) for VEC heads per unit.
+struct LossLanes {
+  int lpr, lpr_log2, nc;
+};
+
+LossLanes loss_lanes(int S, int vec) {
+  LossLanes L{};
+  const int units = (int)ceil_div(S, vec);
+  L.lpr = 1;
+  while (L.lpr < units && L.lpr < 64) L.lpr <<= 1;
+  L.lpr_log2 = 0;
+  while ((1 << L.lpr_log2) < L.lpr) ++L.lpr_log2;
+  const int need = (int)ceil_div(units, L.lpr);
+  L.nc = 1;
+  while (L.nc < need) L.nc <<= 1;
+  return L;
+}
+
+// Item geometry (rows per item R, items) depends on the graph and S only, not on
+// the lane layout a launch picks, so the partials of any launch are summed by
+// the same segmented reduction: R is a multiple of the rows per iteration of
+// every layout S admits.
 struct LossGeom {
-  int lpr, lpr_log2, nc, R, iters;
+  int R, iters;
   int64_t items_cap;
 };
 
 LossGeom loss_geom(const cpra_csr* g, int S) {
   LossGeom G{};
-  G.lpr = 1;
-  while (G.lpr < S && G.lpr < 64) G.lpr <<= 1;
-  G.lpr_log2 = 0;
-  while ((1 << G.lpr_log2) < G.lpr) ++G.lpr_log2;
-  int need = (int)ceil_div(S, G.lpr);
-  G.nc = 1;
-  while (G.nc < need) G.nc <<= 1;
-  const int rows_per_iter = 4 * (64 / G.lpr);
-  // Enough items to fill the GPU several times over, at most 8 row groups each.
-  int64_t it = g->n_nodes / ((int64_t)rows_per_iter * 2048);
+  int rows_per_iter = 4 * (64 / loss_lanes(S, 1).lpr);
+  if (S % 4 == 0) rows_per_iter = std::max(rows_per_iter, 4 * (64 / loss_lanes(S, 4).lpr));
+  // Enough items to give every CU about 16, at most 8 row groups each.
+  const int64_t it = g->n_nodes / ((int64_t)rows_per_iter * 4096);
   G.iters = (int)std::max<int64_t>(1, std::min<int64_t>(8, it));
   G.R = rows_per_iter * G.iters;
   G.items_cap = max_items(g, G.R);
   return G;
 }
+
+inline bool al16(const void* p) { return p == nullptr || reinterpret_cast<uintptr_t>(p) % 16 == 0; }
 
 struct LossWs {
   size_t p_off, item_off, part_off, total;
@@ -378,6 +459,13 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
     ldp = S;
   }
   LossGeom G = loss_geom(g, S);
+  // Four consecutive heads per lane (float4 rows) when every per-head operand allows it.
+  const bool vec4 = S % 4 == 0 && ldz % 4 == 0 && ldp % 4 == 0 && (dZ == nullptr || lddz % 4 == 0) &&
+                    al16(Z) && al16(P) && al16(dZ) && al16(cfg->lambda) &&
+                    (cfg->edge_weight == nullptr || (cfg->ld_edge_weight % 4 == 0 && al16(cfg->edge_weight))) &&
+                    (cfg->node_weight == nullptr || cfg->ld_node_weight == 0 ||
+                     (cfg->ld_node_weight % 4 == 0 && al16(cfg->node_weight)));
+  const LossLanes LN = loss_lanes(S, vec4 ? 4 : 1);
   int32_t* item_ptr = reinterpret_cast<int32_t*>(base + L.item_off);
   float* part = reinterpret_cast<float*>(base + L.part_off);
   CPRA_CHECK(launch_item_ptr(g, G.R, item_ptr, stream));
@@ -387,7 +475,7 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.problem = cfg->problem;
   a.alpha = cfg->alpha;
   a.ddof = cfg->std_ddof;
-  a.lpr_log2 = G.lpr_log2;
+  a.lpr_log2 = LN.lpr_log2;
   a.iters = G.iters;
   a.want_psi = want_terms ? 1 : 0;
   a.row_ptr = g->row_ptr;
@@ -429,21 +517,29 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
                             (ph ? 4.0 * (double)g->nnz * S : 0.0) +
                             4.0 * (double)(S + 2) * G.items_cap;
   ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes);
-  switch (G.nc) {
-#define CPRA_LOSS_CASE(NCV)                                                             \
-  case NCV:                                                                             \
-    if (ph) hipLaunchKernelGGL((k_loss<NCV, true>), dim3(blocks), dim3(256), 0, stream, a); \
-    else hipLaunchKernelGGL((k_loss<NCV, false>), dim3(blocks), dim3(256), 0, stream, a);   \
-    break;
-    CPRA_LOSS_CASE(1)
-    CPRA_LOSS_CASE(2)
-    CPRA_LOSS_CASE(4)
-    CPRA_LOSS_CASE(8)
-    CPRA_LOSS_CASE(16)
-#undef CPRA_LOSS_CASE
-    default:
-      CPRA_FAIL(CPRA_ERR_PARAM, "loss: S too large");
+  bool launched = true;
+#define CPRA_LOSS_LAUNCH(NCV, VECV)                                                              \
+  if (ph) hipLaunchKernelGGL((k_loss<NCV, VECV, true>), dim3(blocks), dim3(256), 0, stream, a);  \
+  else hipLaunchKernelGGL((k_loss<NCV, VECV, false>), dim3(blocks), dim3(256), 0, stream, a);
+  if (vec4) {
+    switch (LN.nc) {
+      case 1: CPRA_LOSS_LAUNCH(1, 4) break;
+      case 2: CPRA_LOSS_LAUNCH(2, 4) break;
+      case 4: CPRA_LOSS_LAUNCH(4, 4) break;
+      default: launched = false;
+    }
+  } else {
+    switch (LN.nc) {
+      case 1: CPRA_LOSS_LAUNCH(1, 1) break;
+      case 2: CPRA_LOSS_LAUNCH(2, 1) break;
+      case 4: CPRA_LOSS_LAUNCH(4, 1) break;
+      case 8: CPRA_LOSS_LAUNCH(8, 1) break;
+      case 16: CPRA_LOSS_LAUNCH(16, 1) break;
+      default: launched = false;
+    }
   }
+#undef CPRA_LOSS_LAUNCH
+  if (!launched) CPRA_FAIL(CPRA_ERR_PARAM, "loss: S too large");
   CPRA_CHECK_LAUNCH("loss");
   if (terms) CPRA_CHECK(loss_terms_reduce(g, cfg, terms, ws, stream));
   return CPRA_OK;
