@@ -8,16 +8,22 @@
 //  * linear-first (out < in, e.g. the S-wide output layer): [Ys | Yn] =
 //    H [Ws; Wn]^T by two GEMMs in one launch, then Y = Ys + M Yn + b with
 //    the ReLU in the aggregation epilogue -- the gather is out wide, not in.
-// Backward (dY = upstream gradient, masked by the ReLU of the layer's output):
-//  * aggregate-first: dWs = dY^T H, dWn = dY^T AX, G = dY [Ws | Wn],
-//    dH = G_s + M^T G_n (masked by H > 0 in the same pass);
-//  * linear-first: T = M^T dY, dWs = dY^T H, dWn = T^T H,
-//    dH = [dY | T] [Ws; Wn] (masked in the GEMM epilogue).
+// Backward (dY = upstream gradient, masked by the ReLU of the layer's output),
+// in an order of its own (either one is valid whichever order the forward took):
+//  * gradient-first (out > in): dWs = dY^T H, dWn = dY^T AX, G = dY [Ws | Wn],
+//    dH = G_s + M^T G_n (masked by H > 0 in the same pass) -- the gather is in
+//    wide;
+//  * transpose-first (out <= in): T = M^T dY, dWs = dY^T H, dWn = T^T H,
+//    dH = [dY | T] [Ws; Wn] (masked in the GEMM epilogue) -- the gather is out
+//    wide, dH is written once instead of G [N, 2 in], and AX is not needed.
+// A square layer (out = in) gathers as many columns either way, so it takes
+// the transpose-first order.
 // db = column sums of dY, added up by the dWs GEMM from the dY tiles it stages
 // in LDS (no separate pass).  The output layer also writes P = sigmoid(Z) in
 // its epilogue, for the loss.  M^T = A D^-1 is applied by the transposed
 // aggregation (not M: the graph need not be regular).  With recompute set,
-// AX is not kept from the forward and is rebuilt in the backward.
+// AX is not kept from the forward and is rebuilt in the backward of the
+// gradient-first layers.
 //
 // Per-graph weights (weight_groups = G > 1): every weight product becomes a
 // grouped GEMM over the batch's graphs -- the forward and input-gradient
@@ -42,7 +48,8 @@ constexpr int kMaxLayers = 16;
 
 struct Layer {
   int in, out;
-  bool lf;  // linear-first
+  bool lf;  // linear-first forward (out < in)
+  bool tf;  // transpose-first backward (out <= in)
   int64_t off_ws, off_wn, off_b;
 };
 
@@ -59,7 +66,7 @@ struct Plan {
   size_t h_off[kMaxLayers];   // saved input of layer k (k >= 1)
   size_t ax_off[kMaxLayers];  // saved M H of aggregate-first layers
   size_t ax_scratch_off;      // recompute buffer
-  size_t yy_off, d_off[2], g_off, t_off, p_off, gemm_off, rows_off;
+  size_t yy_off, d_off[2], g_off, t_off[2], p_off, gemm_off, rows_off;
   size_t gemm_bytes;
   size_t total;
 };
@@ -96,6 +103,7 @@ void make_layers(const cpra_model_cfg* cfg, int N, Plan* p) {
     l.in = d_in;
     l.out = (k == p->L - 1) ? cfg->S : cfg->hidden;
     l.lf = l.out < l.in;
+    l.tf = l.out <= l.in;
     l.off_ws = off;
     off += (int64_t)p->G * l.out * l.in;
     l.off_wn = off;
@@ -152,11 +160,16 @@ void make_plan(const cpra_model_cfg* cfg, const cpra_csr* g, Plan* p) {
     return o;
   };
   const size_t f = sizeof(float);
-  int max_in_after0 = 0, max_in_af = 0, max_out_lf = 0;
+  int max_in_after0 = 0, max_in_af = 0, max_out_lf = 0, max_in_gf = 0, max_out_tf = 0;
   for (int k = 0; k < p->L; ++k) {
     const Layer& l = p->layer[k];
     p->h_off[k] = (k >= 1) ? take((size_t)N * l.in * f) : 0;
     if (k >= 1) max_in_after0 = std::max(max_in_after0, l.in);
+    if (l.tf) {
+      max_out_tf = std::max(max_out_tf, l.out);
+    } else {
+      max_in_gf = std::max(max_in_gf, l.in);
+    }
     if (!l.lf) {
       max_in_af = std::max(max_in_af, l.in);
       p->ax_off[k] = p->recompute ? 0 : take((size_t)N * l.in * f);
@@ -169,8 +182,11 @@ void make_plan(const cpra_model_cfg* cfg, const cpra_csr* g, Plan* p) {
   p->yy_off = max_out_lf ? take((size_t)N * 2 * max_out_lf * f) : 0;
   p->d_off[0] = max_in_after0 ? take((size_t)N * max_in_after0 * f) : 0;
   p->d_off[1] = max_in_after0 ? take((size_t)N * max_in_after0 * f) : 0;
-  p->g_off = max_in_af ? take((size_t)N * 2 * max_in_af * f) : 0;
-  p->t_off = max_out_lf ? take((size_t)N * max_out_lf * f) : 0;
+  p->g_off = max_in_gf ? take((size_t)N * 2 * max_in_gf * f) : 0;
+  // two T buffers, alternating between transpose-first layers, so that a layer's
+  // T does not wait for the side stream to finish reading the previous one
+  p->t_off[0] = max_out_tf ? take((size_t)N * max_out_tf * f) : 0;
+  p->t_off[1] = max_out_tf ? take((size_t)N * max_out_tf * f) : 0;
   p->p_off = take((size_t)N * cfg->S * f);
   size_t gb = 0;
   for (int k = 0; k < p->L; ++k) {
@@ -263,13 +279,23 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
 struct PendingReads {
   const void* buf[4];
   int n = 0;
+  bool full = false;  // more than fit: every write waits (safe, never seen at these depths)
   void add(const void* p) {
-    if (n < 4) buf[n++] = p;
+    if (n < 4) {
+      buf[n++] = p;
+    } else {
+      full = true;
+    }
   }
   bool has(const void* p) const {
+    if (full) return true;
     for (int i = 0; i < n; ++i)
       if (buf[i] == p) return true;
     return false;
+  }
+  void clear() {
+    n = 0;
+    full = false;
   }
 };
 
@@ -303,13 +329,13 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
   auto before_write = [&](const void* buf) -> cpra_status {
     if (side && pending.has(buf)) {
       CPRA_CHECK(join_from(side, st));
-      pending.n = 0;
+      pending.clear();
     }
     return CPRA_OK;
   };
   const float* dY = dZ;
   int64_t lddy = lddz;
-  int ping = 0;
+  int ping = 0, tping = 0;
   void* gemm_ws = p.gemm_bytes ? static_cast<char*>(ws) + p.gemm_off : nullptr;
   for (int k = p.L - 1; k >= p.train_from; --k) {
     const Layer& l = p.layer[k];
@@ -324,8 +350,9 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
     float* dX = (k == 0) ? grads : fptr(ws, p.d_off[ping]);
     const int64_t lddx = l.in;
     const float* mask = (k == 0) ? nullptr : Hk;  // H_k = ReLU output of layer k-1
-    if (l.lf) {
-      float* T = fptr(ws, p.t_off);
+    if (l.tf) {
+      float* T = fptr(ws, p.t_off[tping]);
+      tping ^= 1;
       CPRA_CHECK(before_write(T));
       CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
       if (side) {
