@@ -40,6 +40,11 @@ MODEL_CASES = [
     ("gcn3_lf_first_batch", small_batch, "gcn", 3, 24, 16, 8),
     ("gcn1_single_layer", lambda: random_regular_graph(50, 4, 5), "gcn", 1, 12, 12, 7),
     ("sage3_h128_s64", lambda: random_regular_graph(1000, 20, 6), "sage", 3, 128, 128, 64),
+    # five square layers in a row: transpose-first backwards with alternating T buffers, side-stream
+    # weight gradients still reading the previous T and dY while the next layer runs
+    ("gcn6_h32_deep_square", lambda: random_regular_graph(400, 4, 8), "gcn", 6, 32, 32, 8),
+    # a widening first layer (gradient-first backward) below square layers (transpose-first)
+    ("sage5_widening_then_square", lambda: erdos_renyi_graph(500, 6 / 499, 9), "sage", 5, 16, 32, 8),
 ]
 
 
