@@ -15,7 +15,8 @@ steps, Adam lr 1e-3, FP32.  value = S * |E| / seconds per step.
 
 Besides the JSON line's throughput, the run measures per-kernel durations
 with HIP events (the library's profiler: an event pair around every kernel
-of eager steps queued behind a GPU sleep, so they run back to back), reports the dominant
+of eager steps queued behind a GPU sleep, so they run back to back, on one
+stream so that each kernel has the GPU to itself), reports the dominant
 kernel against its roofline, and times the FP64 CPU oracle on a bounded
 sample of the same workload.
 """
@@ -72,6 +73,9 @@ def make_solver(pr, g, params, per_graph: bool = False, edge_weight=None):
     return sol
 
 
+TIMING = "HIP events around each launch of eager steps on one stream, back to back"
+
+
 def roofline_entry(name, stats, workload):
     """The kernel family's achieved rate from the profiler (algorithmic work per
     launch / average launch time) and, when a counter record for this kernel
@@ -88,12 +92,12 @@ def roofline_entry(name, stats, workload):
         return {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "avg_us": avg_s * 1e6, "launches": launches,
-                "work_per_launch": flops / launches, "work_unit": "FLOP"}
+                "work_per_launch": flops / launches, "work_unit": "FLOP", "timing": TIMING}
     achieved = nbytes / launches / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
             "avg_us": avg_s * 1e6, "launches": launches,
-            "work_per_launch": nbytes / launches, "work_unit": "B"}
+            "work_per_launch": nbytes / launches, "work_unit": "B", "timing": TIMING}
 
 
 def default_tuning_file(workload: str):
@@ -360,15 +364,25 @@ def main():
     if not args.no_profile:
         # per-kernel durations: eager steps with an event pair around every kernel,
         # queued behind a GPU sleep so that the host runs ahead of the GPU and the
-        # kernels execute back to back as in the replayed graph
+        # kernels execute back to back as in the replayed graph, all on one stream
+        # (the side-stream overlap of the timed steps would have two kernels share
+        # the CUs and each event pair time both)
         torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            torch.cuda._sleep(int(2.4e9 * 0.004 * args.profile_steps))  # ~4 ms per step
-            api.profile_begin()
-            for _ in range(args.profile_steps):
-                sol.step(stream)
-            api.profile_stop()
-        torch.cuda.synchronize()
+        overlap = os.environ.get("CPRA_OVERLAP")
+        os.environ["CPRA_OVERLAP"] = "0"
+        try:
+            with torch.cuda.stream(stream):
+                torch.cuda._sleep(int(2.4e9 * 0.004 * args.profile_steps))  # ~4 ms per step
+                api.profile_begin()
+                for _ in range(args.profile_steps):
+                    sol.step(stream)
+                api.profile_stop()
+            torch.cuda.synchronize()
+        finally:
+            if overlap is None:
+                os.environ.pop("CPRA_OVERLAP", None)
+            else:
+                os.environ["CPRA_OVERLAP"] = overlap
         stats = api.profile_end()
         total = sum(v[1] for v in stats.values())
         kernels = {k: {"launches": v[0], "avg_us": v[1] * 1e3 / v[0],

@@ -328,7 +328,8 @@ cpra_status cpra_adam_step(int64_t n, float* params, const float* grads, float* 
  * replayed for every step.  The weight-gradient GEMMs and the loss-term
  * reduction run on a library-owned second stream of the current device,
  * forked from and joined back into `stream` by events (also when captured);
- * CPRA_OVERLAP=0 in the environment keeps all work on `stream`.
+ * CPRA_OVERLAP=0 in the environment (read at every call) keeps all work on
+ * `stream`.
  * cpra_model_backward overlaps its weight gradients the same way.
  * ---------------------------------------------------------------------- */
 typedef struct {

@@ -19,12 +19,11 @@ std::mutex g_side_mu;
 std::map<int, SideStream> g_side;
 }  // namespace
 
+// Read at every call (a host getenv per training step), so that a caller can
+// time the kernels of eager steps alone and still capture overlapped steps.
 bool overlap_enabled() {
-  static const bool on = [] {
-    const char* e = getenv("CPRA_OVERLAP");
-    return !(e != nullptr && e[0] == '0');
-  }();
-  return on;
+  const char* e = getenv("CPRA_OVERLAP");
+  return !(e != nullptr && e[0] == '0');
 }
 
 cpra_status get_side_stream(SideStream** out) {
