@@ -276,11 +276,11 @@ def test_loss_device_schedule_matches_host_gamma():
 
 
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [7, 100003, 5000003])  # one vector; partial pairs; grid-stride passes
 @pytest.mark.parametrize("wd", [0.0, 1e-2])
-def test_adam_step(wd):
+def test_adam_step(wd, n):
     a = api()
     rng = np.random.default_rng(1)
-    n = 100003
     p = rng.standard_normal(n).astype(np.float32)
     gr = rng.standard_normal(n).astype(np.float32)
     m = (0.1 * rng.standard_normal(n)).astype(np.float32)
