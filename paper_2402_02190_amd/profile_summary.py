@@ -80,8 +80,9 @@ def steps(trace_dir: str, bench_json: str, title: str, command: str, out: str) -
             lines += ["", f"Dominant family `{fam}` = `{pat}`: rocprofv3 kernel-trace average over the {n} "
                       f"launches of the profiled eager steps (the launches bench.py times with HIP events) = "
                       f"{sum(d[-n:]) / n:.1f} us; over the {len(d) - n} launches of the replayed/warm-up steps "
-                      f"= {sum(d[:-n]) / max(1, len(d) - n):.1f} us (there the weight-gradient GEMMs of the "
-                      f"side stream run concurrently). The HIP-event average ({rl.get('avg_us', 0):.1f} us) "
+                      f"= {sum(d[:-n]) / max(1, len(d) - n):.1f} us (the profiled eager steps run on one "
+                      f"stream; the replayed steps run the weight-gradient GEMMs on a second stream, beside "
+                      f"the input-gradient GEMMs). The HIP-event average ({rl.get('avg_us', 0):.1f} us) "
                       f"also contains the event packets' own latency around each launch, so the reported "
                       f"achieved rate is a lower bound."]
     text = "\n".join(lines) + "\n"
