@@ -20,13 +20,17 @@ from typing import Dict
 
 import numpy as np
 
-from .objective import edges_of, sigmoid_pair
+from .objective import edges_of
 
 
 def round_solutions(Z: np.ndarray) -> np.ndarray:
-    """X = [P > 0.5] with P = sigmoid(Z), as uint8 [N, S]."""
-    P, _ = sigmoid_pair(Z)
-    return (P > 0.5).astype(np.uint8)
+    """X = [P > 1/2] with P = sigmoid(Z), as uint8 [N, S].
+
+    sigmoid is strictly increasing with sigmoid(0) = 1/2, so P > 1/2 exactly
+    when Z > 0; the decision is taken on Z itself.  (A rounded FP64
+    sigmoid(Z) equals 0.5 for 0 < Z < ~1.1e-16 and would send those entries to
+    0, against the rounding rule's exact meaning.)"""
+    return (np.asarray(Z, dtype=np.float64) > 0.0).astype(np.uint8)
 
 
 def pairwise_hamming_sum(X: np.ndarray) -> int:

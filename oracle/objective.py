@@ -155,12 +155,23 @@ def entropy_term(P: np.ndarray, Q: np.ndarray, alpha: int) -> float:
     return float(np.sum(one_minus_t_pow(P, Q, alpha)))
 
 
+def identical_rows(P: np.ndarray) -> np.ndarray:
+    """Nodes whose S heads hold one and the same value (max == min over the row)."""
+    return P.max(axis=1) == P.min(axis=1)
+
+
 def row_std(P: np.ndarray, ddof: int = 0) -> np.ndarray:
-    """STD_s[P_is] per node i, two-pass: mean first, then squared deviations."""
+    """STD_s[P_is] per node i, two-pass: mean first, then squared deviations.
+
+    A row whose heads are all equal has STD exactly 0.  The rounded mean of S
+    equal values need not equal them (e.g. ten copies of 0.3 sum to
+    2.9999999999999996), which would leave a spurious sigma of ~1e-17, so such
+    rows are set to 0 by their definition rather than by the two passes."""
     S = P.shape[1]
     mu = P.sum(axis=1) / S
     dev = P - mu[:, None]
-    return np.sqrt(np.sum(dev * dev, axis=1) / (S - ddof))
+    sig = np.sqrt(np.sum(dev * dev, axis=1) / (S - ddof))
+    return np.where(identical_rows(P), 0.0, sig)
 
 
 def diversity_term(P: np.ndarray, ddof: int = 0) -> float:
@@ -230,7 +241,9 @@ def grad_wrt_P(P: np.ndarray, Q: np.ndarray, graph, problem: str, lam, gamma: fl
                   MaxCut sum_{j in N(i)} A_ij (2 P_js - 1)
     annealing:    gamma * d/dP (1 - (2P-1)^alpha) = -2 alpha gamma (2P-1)^(alpha-1)
     diversity:    nu * dPsi/dP_is = -nu * S (P_is - mu_i) / ((S - ddof) sigma_i),
-                  taken as 0 where sigma_i = 0 (a subgradient of the norm).
+                  taken as 0 where sigma_i = 0, i.e. where all heads of node i are
+                  equal (0 is a subgradient of the norm there; any subgradient sums
+                  to 0 over the heads, as the gradient does wherever sigma_i > 0).
     """
     N, S = P.shape
     if edge_weight is None:

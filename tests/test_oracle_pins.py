@@ -146,6 +146,49 @@ def test_std_matches_numpy_ddof():
     np.testing.assert_allclose(objective.row_std(P, 1), np.std(P, axis=1, ddof=1), rtol=1e-13)
 
 
+def _psi_grad(P, ddof=0, nu=1.0):
+    """nu * dPsi/dP alone: MaxCut on an edgeless graph at gamma = 0 has no other term."""
+    from workloads import csr_from_edges
+    N = P.shape[0]
+    g = csr_from_edges(N, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    return objective.grad_wrt_P(P, 1.0 - P, g, "maxcut", None, 0.0, 2, nu, ddof)
+
+
+@pytest.mark.parametrize("ddof", [0, 1])
+def test_psi_gradient_sums_to_zero_over_heads(ddof):
+    """sigma_i does not change when one constant is added to every head of node i,
+    so every (sub)gradient of Psi sums to zero over the heads of each node."""
+    rng = np.random.default_rng(11 + ddof)
+    for S in (2, 3, 7, 32, 100):
+        P = rng.random((40, S))
+        P[::5] = P[::5, :1]  # every fifth row: all heads equal
+        G = _psi_grad(P, ddof, nu=0.7)
+        scale = np.abs(G).sum(axis=1)
+        assert np.all(np.abs(G.sum(axis=1)) <= 1e-12 * np.maximum(scale, 1e-300))
+        assert np.all(scale[1::5] > 0)  # the other rows do carry a gradient
+
+
+@pytest.mark.parametrize("S", [3, 7, 100])
+def test_psi_identical_heads_give_exact_zero(S):
+    """Heads that coincide at a node: sigma_i = 0, Psi_i = 0 and dPsi_i = 0 exactly,
+    for non-dyadic values whose rounded mean differs from the value itself."""
+    rng = np.random.default_rng(S)
+    vals = np.concatenate([[0.3, 0.1, 0.7, 1.0 / 3.0], rng.random(60)])
+    P = np.repeat(vals[:, None], S, axis=1)
+    mean_off = np.sum(P.sum(axis=1) / S != vals)
+    assert mean_off > 0  # the two-pass mean alone would leave sigma > 0 on these rows
+    for ddof in (0, 1):
+        assert np.all(objective.row_std(P, ddof) == 0.0)
+        assert objective.diversity_term(P, ddof) == 0.0
+        assert np.all(_psi_grad(P, ddof) == 0.0)
+    # the same rows among distinct ones: only the distinct rows move
+    Q = np.vstack([P, rng.random((10, S))])
+    G = _psi_grad(Q, 0)
+    assert np.all(G[: vals.size] == 0.0) and np.all(np.abs(G[vals.size:]).sum(axis=1) > 0)
+    np.testing.assert_allclose(objective.row_std(Q[vals.size:]), np.std(Q[vals.size:], axis=1),
+                               rtol=1e-13)
+
+
 def test_dscore_definition():
     X = np.array([[1, 0, 1], [0, 0, 1], [1, 1, 1], [0, 1, 0]], dtype=np.uint8)
     # columns 1010, 0011, 1110: d_H(0,1)=2, d_H(0,2)=1, d_H(1,2)=3 -> 6 ; DScore = 2*6/(4*3*2)
@@ -413,8 +456,24 @@ def test_penalty_minimisers_are_maximum_independent_sets(seed):
 # ---------------------------------------------------------------------------
 
 def test_rounding_tie_goes_to_zero():
-    Z = np.array([[0.0, 1e-300, -1e-300, 3.0]])
-    assert evaluate.round_solutions(Z).tolist() == [[0, 0, 0, 1]]
+    Z = np.array([[0.0, -0.0, 1e-300, -1e-300, 3.0]])
+    assert evaluate.round_solutions(Z).tolist() == [[0, 0, 1, 0, 1]]
+
+
+def test_rounding_matches_exact_sigmoid_threshold():
+    """x = [sigmoid(z) > 1/2] decided in exact decimal arithmetic (2,000 digits,
+    enough to hold 1 - 2^-1074 exactly) for logits at and around the tie,
+    subnormals included: the rule P <= 0.5 -> 0, P > 0.5 -> 1 of the
+    training-setting appendix, with sigmoid evaluated without rounding."""
+    from decimal import Decimal, localcontext
+    zs = [0.0, -0.0, 5e-324, -5e-324, 1e-320, 1e-300, -1e-300, 1e-20, 1e-17, 1e-16, 1.1e-16,
+          2.3e-16, -2.3e-16, 1e-8, -1e-8, 0.5, -7.0, 40.0]
+    with localcontext() as ctx:
+        ctx.prec = 2000
+        exact = [int(Decimal(1) / (1 + (-Decimal(z)).exp()) > Decimal("0.5")) for z in zs]
+    got = evaluate.round_solutions(np.array([zs])).tolist()[0]
+    assert got == exact
+    assert exact[:4] == [0, 0, 1, 0]
 
 
 def test_evaluate_against_networkx():
