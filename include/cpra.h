@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define CPRA_ABI_VERSION 7
+#define CPRA_ABI_VERSION 8
 
 typedef void* cpra_stream_t; /* hipStream_t */
 
@@ -181,7 +181,9 @@ cpra_status cpra_gemm_grouped(const cpra_csr* g, int32_t mode, int32_t trans_b, 
  *   weights, A_ijs: one instance C_s per head on the graph's pattern (Sec. 3.1
  *   solves S instances at once; the multi-instance appendix, 27 instances of
  *   one structure), a zero leaving the edge out of head s's instance.
- *   Psi    = -S * sum_i STD_s[P_is]  (population STD, or sample STD if std_ddof = 1)
+ *   Psi    = -S * sum_i STD_s[P_is]  (population STD, or sample STD if std_ddof = 1);
+ *            STD_s[P_is] = 0 and dPsi/dP_i: = 0 exactly where all heads of node i
+ *            are equal (0 is a subgradient of the norm there)
  * Output dZ = dR/dZ and, per graph g of the batch, terms[g*(S+2) + c]:
  *   c < S: l_c of graph g;  c = S: sum of (1-(2P-1)^alpha) over the graph;
  *   c = S+1: Psi of the graph.  R = sum_s terms[s] + gamma*terms[S] + nu*terms[S+1].
@@ -225,6 +227,15 @@ cpra_status cpra_loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg,
                               const float* Z, int64_t ldz, const float* P, int64_t ldp,
                               float* dZ, int64_t lddz, double* terms,
                               void* ws, size_t ws_bytes, cpra_stream_t stream);
+
+/* The total relaxed loss R of Sec. 3.1 / 3.3 from the per-graph terms that
+ * cpra_loss_fwd_bwd writes: R = sum_g (sum_s terms[g][s] + gamma * terms[g][S]
+ * + nu * terms[g][S+1]), summed in FP64 on the device in a fixed order (heads
+ * in order within a graph, graphs in order), so it needs no host copy.
+ * terms: device [n_graphs, S+2] doubles; R: device, one double.
+ * CPRA_ERR_NULL / CPRA_ERR_PARAM for NULL pointers, n_graphs < 1 or S < 1. */
+cpra_status cpra_loss_total(int32_t n_graphs, int32_t S, const double* terms, double gamma,
+                            double nu, double* R, cpra_stream_t stream);
 
 /* P[i,s] = sigmoid(Z[i,s]) (GNN appendix: sigmoid after the last layer). */
 cpra_status cpra_sigmoid(int32_t N, int32_t S, const float* Z, int64_t ldz, float* P, int64_t ldp,
@@ -332,10 +343,48 @@ cpra_status cpra_adam_step(int64_t n, float* params, const float* grads, float* 
  * `stream`.
  * cpra_model_backward overlaps its weight gradients the same way.
  * ---------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------
+ * Early stopping (Sec. 4.1 Implementation; training-setting appendix: the
+ * summed head loss and the annealing term are monitored with a tolerance of
+ * 1e-5 and a patience of 10^3 epochs).  Monitored per step t (summed over the
+ * graphs of a batch):  L_t = sum_s l_s(P_t),  Phi_t = gamma_t * sum_{i,s}
+ * (1 - (2 P_is - 1)^alpha).  Step t (t >= 1) is stalled when neither fell by
+ * more than the tolerance (the paper's tolerance is absolute; relative = 1
+ * scales it by the previous value's magnitude):
+ *   L_t - L_{t-1} >= -tol_L  and  Phi_t - Phi_{t-1} >= -tol_Phi,
+ *   tol_X = tol (absolute) or tol |X_{t-1}| (relative).
+ * After `patience` consecutive stalled steps the rule fires at that step: its
+ * parameter update is skipped, `stopped` is set and the step counter stops
+ * advancing, so every later step (eager or replayed) leaves the parameters,
+ * the Adam moments and the counter as they are.  The state lives on the
+ * device and is updated inside the step, so a captured step carries the
+ * rule; the host reads `stopped` whenever it likes (cpra_early_stop_reset
+ * initialises it).  Needs terms and a step_counter in cpra_train_step.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double prev_head;  /* L of the last evaluated step */
+  double prev_phi;   /* Phi of the last evaluated step */
+  int32_t stalled;   /* consecutive stalled steps so far */
+  int32_t stopped;   /* 1 once the rule fired */
+  int32_t stop_step; /* 0-based index t of the step that fired it, -1 before */
+  int32_t seen;      /* steps evaluated */
+} cpra_early_stop_state;
+
+typedef struct {
+  double tol;                   /* tolerance, >= 0 (the paper: 1e-5) */
+  int32_t patience;             /* stalled steps that stop training, >= 1 (the paper: 1000) */
+  int32_t relative;             /* 0: absolute tolerance (the paper's); 1: relative */
+  cpra_early_stop_state* state; /* device, caller-owned; NULL: no early stopping */
+} cpra_early_stop_cfg;
+
+/* state = {0, 0, 0, 0, -1, 0} by a kernel on `stream` (valid inside a capture). */
+cpra_status cpra_early_stop_reset(cpra_early_stop_state* state, cpra_stream_t stream);
+
 typedef struct {
   cpra_model_cfg model;
   cpra_loss_cfg loss;
   cpra_adam_cfg adam;
+  cpra_early_stop_cfg early_stop; /* state == NULL: train every step */
 } cpra_step_cfg;
 
 size_t cpra_train_step_workspace_bytes(const cpra_csr* g, const cpra_step_cfg* cfg);

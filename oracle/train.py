@@ -34,6 +34,34 @@ def gamma_paper(t: int, gamma0: float, rate: float) -> float:
     return float(gamma0 + rate * t)
 
 
+def early_stop_step(head, phi, tol: float, patience: int,
+                    relative: bool = False) -> Optional[int]:
+    """Early stopping (Sec. 4.1 Implementation; training-setting appendix): the
+    summed head loss L_t = sum_s l_hat(P_:s) and the annealing term
+    Phi_t = gamma_t * S(P_t) are monitored with a tolerance and a patience.
+
+    Reading of the rule: step t >= 1 is stalled when neither monitored value fell
+    by more than the tolerance -- absolute (the paper states a plain tolerance),
+    or with ``relative`` scaled by the previous value's magnitude:
+        L_t - L_{t-1} >= -tol_L  and  Phi_t - Phi_{t-1} >= -tol_Phi;
+    training stops at the first step that completes `patience` consecutive
+    stalled steps.  Returns that step's index, or None if the sequences end first.
+    """
+    run = 0
+    for t in range(1, len(head)):
+        dl = head[t] - head[t - 1]
+        dp = phi[t] - phi[t - 1]
+        tl = tol * abs(head[t - 1]) if relative else tol
+        tp = tol * abs(phi[t - 1]) if relative else tol
+        if dl >= -tl and dp >= -tp:
+            run += 1
+            if run >= patience:
+                return t
+        else:
+            run = 0
+    return None
+
+
 def adam_update(theta: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int,
                 lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
                 weight_decay: float = 0.0):

@@ -54,8 +54,19 @@ class AdamCfg(C.Structure):
                 ("eps", C.c_double), ("weight_decay", C.c_double)]
 
 
+class EarlyStopState(C.Structure):
+    _fields_ = [("prev_head", C.c_double), ("prev_phi", C.c_double), ("stalled", C.c_int32),
+                ("stopped", C.c_int32), ("stop_step", C.c_int32), ("seen", C.c_int32)]
+
+
+class EarlyStopCfg(C.Structure):
+    _fields_ = [("tol", C.c_double), ("patience", C.c_int32), ("relative", C.c_int32),
+                ("state", C.c_void_p)]
+
+
 class StepCfg(C.Structure):
-    _fields_ = [("model", ModelCfg), ("loss", LossCfg), ("adam", AdamCfg)]
+    _fields_ = [("model", ModelCfg), ("loss", LossCfg), ("adam", AdamCfg),
+                ("early_stop", EarlyStopCfg)]
 
 
 class MpnnCfg(C.Structure):
@@ -89,6 +100,7 @@ PROTOTYPES = {
                                  P, I64, P, I64, I32, P, SZ, P]),
     "cpra_loss_workspace_bytes": (SZ, [PCsr, PLoss]),
     "cpra_loss_fwd_bwd": (None, [PCsr, PLoss, P, I64, P, I64, P, I64, P, P, SZ, P]),
+    "cpra_loss_total": (None, [I32, I32, P, C.c_double, C.c_double, P, P]),
     "cpra_sigmoid": (None, [I32, I32, P, I64, P, I64, P]),
     "cpra_model_param_count": (I64, [PModel, I32]),
     "cpra_model_param_offsets": (None, [PModel, I32, C.POINTER(I64)]),
@@ -98,6 +110,7 @@ PROTOTYPES = {
     "cpra_model_saved_activation": (None, [PCsr, PModel, P, SZ, I32, C.POINTER(C.c_void_p),
                                            C.POINTER(I64)]),
     "cpra_adam_step": (None, [I64, P, P, P, P, PAdam, I32, P, P]),
+    "cpra_early_stop_reset": (None, [P, P]),
     "cpra_train_step_workspace_bytes": (SZ, [PCsr, PStep]),
     "cpra_train_step": (None, [PCsr, PStep, P, P, P, P, P, P, P, I32, P, P, SZ, P]),
     "cpra_round_eval_workspace_bytes": (SZ, [PCsr, I32]),

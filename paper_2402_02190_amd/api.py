@@ -14,8 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (GCN, MAXCUT, MIS, SAGE, AdamCfg, CpraError, Csr, LossCfg, ModelCfg,  # noqa: F401
-                   MpnnCfg, MpnnStepCfg, StepCfg, call)
+from ._lib import (GCN, MAXCUT, MIS, SAGE, AdamCfg, CpraError, Csr, EarlyStopCfg,  # noqa: F401
+                   EarlyStopState, LossCfg, ModelCfg, MpnnCfg, MpnnStepCfg, StepCfg, call)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -225,6 +225,29 @@ def loss_fwd_bwd(g, cfg: LossCfg, Z: torch.Tensor, dZ: Optional[torch.Tensor],
     call("cpra_loss_fwd_bwd", _csr(g), C.byref(cfg), _ptr(Z), Z.stride(0), _ptr(P),
          0 if P is None else P.stride(0), _ptr(dZ), 0 if dZ is None else dZ.stride(0),
          _ptr(terms), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def loss_total(terms: torch.Tensor, gamma: float, nu: float, R: torch.Tensor, stream=None):
+    """R (device, one float64) = the total loss from the per-graph terms [n_graphs, S+2]."""
+    G, S2 = terms.shape
+    call("cpra_loss_total", G, S2 - 2, _ptr(terms), float(gamma), float(nu), _ptr(R),
+         _stream(stream))
+    return R
+
+
+def early_stop_reset(state: torch.Tensor, stream=None):
+    """Initialise an early-stopping state (a device buffer of at least
+    sizeof(cpra_early_stop_state) bytes)."""
+    if state.numel() * state.element_size() < C.sizeof(EarlyStopState):
+        raise ValueError("early-stopping state buffer too small")
+    call("cpra_early_stop_reset", _ptr(state), _stream(stream))
+
+
+def early_stop_read(state: torch.Tensor) -> dict:
+    """The state as a dict (copies 32 bytes to the host; synchronises)."""
+    raw = state.detach().cpu().numpy().tobytes()[: C.sizeof(EarlyStopState)]
+    st = EarlyStopState.from_buffer_copy(raw)
+    return {k: getattr(st, k) for k, _ in EarlyStopState._fields_}
 
 
 def sigmoid(Z: torch.Tensor, P: torch.Tensor, stream=None):

@@ -23,6 +23,7 @@ struct AdamArgs {
   int t;
   const int32_t* step_counter;
   int t_offset;  // t = *step_counter + t_offset when step_counter is given
+  const int32_t* stop_flag;  // optional: no update while *stop_flag != 0 (early stopping)
 };
 
 struct AdamCoef {
@@ -40,6 +41,7 @@ __device__ inline void adam_one(float& p, float g, float& m, float& v, const Ada
 
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  if (a.stop_flag && *a.stop_flag) return;  // uniform across the grid
   __shared__ float s_bc[2];
   if (threadIdx.x == 0) {
     int t = a.step_counter ? (*a.step_counter + a.t_offset) : a.t;
@@ -83,13 +85,13 @@ inline bool al16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 
 
 cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
                       const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
-                      hipStream_t stream, int t_offset) {
+                      hipStream_t stream, int t_offset, const int32_t* stop_flag) {
   if (n == 0) return CPRA_OK;
   AdamArgs a{n, params, grads, m, v,
              (float)cfg->lr, (float)cfg->beta1, (float)(1.0 - cfg->beta1),
              (float)cfg->beta2, (float)(1.0 - cfg->beta2), (float)cfg->eps,
              (float)(1.0 - cfg->lr * cfg->weight_decay), cfg->beta1, cfg->beta2,
-             t, step_counter, t_offset};
+             t, step_counter, t_offset, stop_flag};
   const bool vec = al16(params) && al16(grads) && al16(m) && al16(v);
   const int64_t work = vec ? (n + 3) / 4 : n;
   const int blocks = (int)std::min<int64_t>(ceil_div(work, 256), 256 * 8);

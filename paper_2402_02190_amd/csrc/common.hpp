@@ -184,10 +184,18 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
                          void* ws, size_t ws_bytes, hipStream_t stream, bool want_terms = false);
 cpra_status check_loss_cfg_public(const cpra_csr* g, const cpra_loss_cfg* cfg);
 
-// With step_counter, Adam's t = *step_counter + t_offset.
+// With step_counter, Adam's t = *step_counter + t_offset.  stop_flag (optional,
+// device): the update is skipped while *stop_flag != 0.
 cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, float* v,
                       const cpra_adam_cfg* cfg, int32_t t, const int32_t* step_counter,
-                      hipStream_t stream, int t_offset = 1);
+                      hipStream_t stream, int t_offset = 1, const int32_t* stop_flag = nullptr);
+
+// Early stopping (early_stop.hip): checks of the config, and the per-step
+// update of the device state from the step's complete per-graph terms, which
+// also advances the step counter unless the rule has fired.
+cpra_status check_early_stop_cfg(const cpra_early_stop_cfg* es);
+cpra_status early_stop_update(const cpra_csr* g, const cpra_loss_cfg* lc, const double* terms,
+                              const cpra_early_stop_cfg* es, int32_t* counter, hipStream_t stream);
 cpra_status check_adam_cfg(const cpra_adam_cfg* cfg);
 
 // Side stream of the current device (see streams.hip).  fork_to makes the side

@@ -16,6 +16,14 @@ namespace cpra {
 
 namespace {
 
+// x = [Z > 0] decided on the bit pattern: +0 and negatives (sign bit set) give
+// 0, every positive value from the smallest subnormal to +inf gives 1, NaN 0.
+// The result does not depend on the wavefront's denormal mode.
+__device__ inline bool rounds_to_one(float z) {
+  const int32_t b = __float_as_int(z);
+  return b > 0 && b <= 0x7f800000;
+}
+
 struct EvalArgs {
   int n, S, problem, lpr_log2;
   const int32_t* row_ptr;
@@ -77,7 +85,7 @@ __global__ __launch_bounds__(256) void k_round_eval(EvalArgs a) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int s = c * lpr + cl;
-      x[c] = (active && s < S && a.Z[(int64_t)row * a.ldz + s] > 0.0f) ? 1 : 0;
+      x[c] = (active && s < S && rounds_to_one(a.Z[(int64_t)row * a.ldz + s])) ? 1 : 0;
       k_row += x[c];
       if (active && s < S && a.X) a.X[(int64_t)row * a.ldx + s] = (uint8_t)x[c];
     }
@@ -104,7 +112,7 @@ __global__ __launch_bounds__(256) void k_round_eval(EvalArgs a) {
           if (s >= S) continue;
           const float w = a.edge_w ? a.edge_w[(int64_t)k * a.ld_ew + s] : w0;
           if (a.edge_w && w == 0.0f) continue;  // not an edge of head s's instance
-          const int xj = a.Z[(int64_t)j * a.ldz + s] > 0.0f ? 1 : 0;
+          const int xj = rounds_to_one(a.Z[(int64_t)j * a.ldz + s]) ? 1 : 0;
           if (mis) {
             c_vio[c] += x[c] & xj;
           } else if (x[c] != xj) {

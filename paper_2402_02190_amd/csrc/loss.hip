@@ -13,6 +13,7 @@
 //              evaluated as 4 P Q sum_{k<alpha/2} t^(2k); d(gamma phi)/dP = -2 alpha gamma t^(alpha-1)
 //   diversity: Psi_i = -S sigma_i over the heads of node i,
 //              dPsi/dP_is = -S (P_is - mu_i) / ((S - ddof) sigma_i), 0 where sigma_i = 0
+//              (exactly where all heads of node i are equal)
 //   dZ_is = dR/dP_is * P_is * Q_is.
 //
 // Layout: a wavefront holds 64/LPR nodes, the LPR lanes of a node cover its
@@ -246,8 +247,13 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
         q[c].v[x] = zz >= 0.0f ? e * r : r;
       }
 
-    // Diversity statistics of the node across its heads (two passes).
-    float mu = 0.0f, sig = 0.0f, inv_dev_scale = 0.0f;
+    // Diversity statistics of the node across its heads: mean, then deviations
+    // corrected by their own mean (the corrected two-pass variance of Chan, Golub
+    // and LeVeque), so that a deviation keeps its relative accuracy when sigma is
+    // far below the mean.  A node whose heads are all equal has sigma = 0 (and a
+    // zero gradient) by definition: the rounded mean of equal values need not
+    // equal them, which would leave a spurious sigma of a few ulps.
+    float mu = 0.0f, dmu = 0.0f, sig = 0.0f, inv_dev_scale = 0.0f;
     if (stats) {
       float sp = 0.0f;
 #pragma unroll
@@ -257,17 +263,27 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
           for (int x = 0; x < VEC; ++x) sp += p[c].v[x];
       sp = wave_sum_xor(sp, 1, lpr);
       mu = sp / (float)S;
-      float sd = 0.0f;
+      const float first = __shfl(p[0].v[0], lane & ~(lpr - 1), 64);  // head 0 of the node
+      float sd = 0.0f, s1 = 0.0f;
+      int differ = 0;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (uok[c])
 #pragma unroll
           for (int x = 0; x < VEC; ++x) {
             const float d = p[c].v[x] - mu;
+            s1 += d;
             sd += d * d;
+            differ |= p[c].v[x] != first;
           }
-      sd = wave_sum_xor(sd, 1, lpr);
-      sig = sqrtf(sd / (float)(S - a.ddof));
+      for (int m = 1; m < lpr; m <<= 1) {
+        s1 += __shfl_xor(s1, m, 64);
+        sd += __shfl_xor(sd, m, 64);
+        differ |= __shfl_xor(differ, m, 64);
+      }
+      dmu = s1 / (float)S;
+      sd = fmaxf(sd - s1 * dmu, 0.0f);
+      sig = differ ? sqrtf(sd / (float)(S - a.ddof)) : 0.0f;
       inv_dev_scale = sig > 0.0f ? -(float)S / ((float)(S - a.ddof) * sig) : 0.0f;
       if (active && cl == 0) psi += -(float)S * sig;
     }
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
           gr = 2.0f * aa - wdc;
         }
         gr -= two_alpha_gamma * t_am1;
-        if (diverse) gr += a.nu * inv_dev_scale * (pp - mu);
+        if (diverse) gr += a.nu * inv_dev_scale * ((pp - mu) - dmu);
         hl[c].v[x] += l;
         ent += phi;
         dz.v[x] = gr * pp * qq;
@@ -558,9 +574,42 @@ cpra_status loss_terms_reduce(const cpra_csr* g, const cpra_loss_cfg* cfg, doubl
                                advance);
 }
 
+// R = sum_g (sum_s t[g][s] + gamma t[g][S] + nu t[g][S+1]): thread i sums the
+// graphs i, i + 256, ... in order, then a fixed tree over the threads.
+__global__ __launch_bounds__(256) void k_loss_total(int n_graphs, int S, const double* __restrict__ t,
+                                                    double gamma, double nu, double* R) {
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < n_graphs; g += 256) {
+    const double* row = t + (int64_t)g * (S + 2);
+    double h = 0.0;
+    for (int s = 0; s < S; ++s) h += row[s];
+    acc += h + gamma * row[S] + nu * row[S + 1];
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) R[0] = sh[0];
+}
+
 }  // namespace cpra
 
 extern "C" {
+
+cpra_status cpra_loss_total(int32_t n_graphs, int32_t S, const double* terms, double gamma,
+                            double nu, double* R, cpra_stream_t stream) {
+  if (terms == nullptr || R == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "loss_total: NULL pointer");
+  if (n_graphs < 1 || S < 1) CPRA_FAIL(CPRA_ERR_PARAM, "loss_total: n_graphs and S must be >= 1");
+  if (!std::isfinite(gamma) || !std::isfinite(nu))
+    CPRA_FAIL(CPRA_ERR_NONFINITE, "loss_total: gamma or nu is not finite");
+  hipLaunchKernelGGL(cpra::k_loss_total, dim3(1), dim3(256), 0, cpra::as_stream(stream), n_graphs, S,
+                     terms, gamma, nu, R);
+  CPRA_CHECK_LAUNCH("loss_total");
+  return CPRA_OK;
+}
 
 size_t cpra_loss_workspace_bytes(const cpra_csr* g, const cpra_loss_cfg* cfg) {
   if (g == nullptr || cfg == nullptr || cfg->S < 1) return 0;

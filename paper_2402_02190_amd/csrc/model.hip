@@ -553,6 +553,10 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   lc.step_counter = step_counter;
   CPRA_CHECK(check_loss_cfg_public(g, &lc));
   CPRA_CHECK(check_adam_cfg(&cfg->adam));
+  CPRA_CHECK(check_early_stop_cfg(&cfg->early_stop));
+  const bool es = cfg->early_stop.state != nullptr;
+  if (es && (terms == nullptr || step_counter == nullptr))
+    CPRA_FAIL(CPRA_ERR_PARAM, "train_step: early stopping needs terms and a step counter");
   if (cfg->loss.S != cfg->model.S) CPRA_FAIL(CPRA_ERR_PARAM, "train_step: loss.S != model.S");
   if (step_counter == nullptr && t < 1) CPRA_FAIL(CPRA_ERR_PARAM, "train_step: t must be >= 1");
   if (g->n_nodes == 0) return CPRA_OK;
@@ -579,8 +583,12 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   // runs after the join.  (Adam cannot be split across the streams: the side
   // stream's first-layer weight gradient reads the embedding, and the main
   // stream's last products read the layer weights.)
+  // With early stopping the rule's update follows the reduction and advances
+  // the counter itself (unless the rule has fired).
   std::function<cpra_status(hipStream_t)> terms_task = [&](hipStream_t s2) {
-    return loss_terms_reduce(g, &lc, terms, loss_ws, s2, step_counter);
+    CPRA_CHECK(loss_terms_reduce(g, &lc, terms, loss_ws, s2, es ? nullptr : step_counter));
+    if (es) CPRA_CHECK(early_stop_update(g, &lc, terms, &cfg->early_stop, step_counter, s2));
+    return CPRA_OK;
   };
   if (terms) {
     if (!side) CPRA_CHECK(terms_task(st));
@@ -593,7 +601,8 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   // only the trainable tail [first trained layer, end) when the encoder is frozen
   const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : 0;
   CPRA_CHECK(adam_step(p.n_params - a0, params + a0, grads + a0, m + a0, v + a0, &cfg->adam, t,
-                       step_counter, st, /*t_offset=*/0));
+                       step_counter, st, /*t_offset=*/0,
+                       es ? &cfg->early_stop.state->stopped : nullptr));
   return CPRA_OK;
 }
 

@@ -252,6 +252,47 @@ class CPRASolver:
             for _ in range(steps):
                 self.step()
 
+    # -- early stopping ------------------------------------------------------
+    def enable_early_stopping(self, tol: float = 1e-5, patience: int = 1000,
+                              relative: bool = False) -> None:
+        """Turn on the device-side stopping rule of Sec. 4.1 (the summed head loss and the
+        annealing term monitored with a tolerance -- absolute, as the paper's, or relative
+        to the previous value -- and a patience; see cpra_early_stop_cfg): every later
+        step, eager or replayed, updates the rule's state, and a step that fires it
+        leaves the parameters as they are."""
+        if getattr(self, "_es_state", None) is None:
+            self._es_state = torch.zeros(64, dtype=torch.uint8, device=self.device)
+        api.early_stop_reset(self._es_state)
+        self.step_cfg.early_stop = api.EarlyStopCfg(float(tol), int(patience), int(relative),
+                                                    self._es_state.data_ptr())
+        self.close()  # a captured step would keep the old configuration
+
+    def disable_early_stopping(self) -> None:
+        self.step_cfg.early_stop = api.EarlyStopCfg(0.0, 0, 0, None)
+        self.close()
+
+    def early_stop_state(self) -> Dict[str, object]:
+        """{prev_head, prev_phi, stalled, stopped, stop_step, seen} (synchronises)."""
+        if getattr(self, "_es_state", None) is None:
+            raise RuntimeError("early stopping is not enabled")
+        return api.early_stop_read(self._es_state)
+
+    def run_with_early_stopping(self, steps: int, check_every: int = 50):
+        """Replay up to `steps` steps, reading the device's stop flag (4 bytes) every
+        `check_every` steps.  Returns (steps replayed, index of the step that fired the
+        rule or None).  Steps replayed after the rule fired change nothing."""
+        if self.step_cfg.early_stop.state is None:
+            raise RuntimeError("enable_early_stopping() first")
+        done = 0
+        while done < steps:
+            n = min(check_every, steps - done)
+            self.replay(n)
+            done += n
+            st = self.early_stop_state()
+            if st["stopped"]:
+                return done, int(st["stop_step"])
+        return done, None
+
     def run_until_binary(self, steps: int, eps: float = 1e-4, check_every: int = 50) -> int:
         """Replay up to `steps` steps, stopping early once the annealing term per entry,
         S(P) / (N S), falls below eps (checked every `check_every` steps: the

@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = _lib.lib()
-    assert lib.cpra_abi_version() == 7
+    assert lib.cpra_abi_version() == 8
     for code, name in _lib.STATUS.items():
         assert lib.cpra_status_string(code).decode() == name
 
@@ -58,6 +58,9 @@ int main(void) {
          offsetof(cpra_loss_cfg, step_counter), offsetof(cpra_loss_cfg, T),
          offsetof(cpra_step_cfg, adam), offsetof(cpra_loss_cfg, edge_weight));
   printf("%zu\\n", offsetof(cpra_csr, col_inv_deg));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(cpra_early_stop_state), sizeof(cpra_early_stop_cfg),
+         offsetof(cpra_step_cfg, early_stop), offsetof(cpra_early_stop_cfg, state),
+         offsetof(cpra_early_stop_state, stop_step));
   return 0;
 }
 """)
@@ -73,6 +76,9 @@ int main(void) {
                     _lib.LossCfg.step_counter.offset, _lib.LossCfg.T.offset, _lib.StepCfg.adam.offset,
                     _lib.LossCfg.edge_weight.offset]
     assert int(lines[2]) == _lib.Csr.col_inv_deg.offset
+    assert [int(x) for x in lines[3].split()] == [
+        C.sizeof(_lib.EarlyStopState), C.sizeof(_lib.EarlyStopCfg), _lib.StepCfg.early_stop.offset,
+        _lib.EarlyStopCfg.state.offset, _lib.EarlyStopState.stop_step.offset]
 
 
 def _validate(rp, ci, w=None):

@@ -6,9 +6,10 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import assert_close_array, need_gpu, say, to_dev
+from helpers import assert_close_array, assert_close_scalar, need_gpu, say, to_dev
 from oracle import evaluate as oev
 from oracle import gnn as ognn
+from oracle import objective as oobj
 from oracle import train as otrain
 from oracle import warmstart as W
 from workloads import CSRGraph, csr_from_edges, disjoint_union, init_params, random_channels, \
@@ -36,6 +37,16 @@ def star(leaves):
     return csr_from_edges(leaves + 1, np.zeros(leaves, np.int64), np.arange(1, leaves + 1))
 
 
+def _head_scale(Z, g, problem, lam):
+    """Sum of |summands| of each head's relaxed objective (its conditioning scale)."""
+    P, _ = oobj.sigmoid_pair(Z)
+    ei, ej, w = oobj.edges_of(g.row_ptr, g.col_idx, g.weight)
+    pair = np.sum(np.abs(w)[:, None] * P[ei] * P[ej], axis=0)
+    if problem == "mis":
+        return P.sum(axis=0) + np.abs(np.asarray(lam, dtype=np.float64)) * pair
+    return 2.0 * pair + np.sum(np.abs(w)[:, None] * (P[ei] + P[ej]), axis=0)
+
+
 def _step_vs_oracle(g, kind="sage", L=2, H=32, S=8, problem="mis", what=""):
     api, CPRAConfig, CPRASolver = mods()
     dg = api.DeviceGraph.from_csr(g)
@@ -61,8 +72,16 @@ def _step_vs_oracle(g, kind="sage", L=2, H=32, S=8, problem="mis", what=""):
             else:
                 assert_close_array(gg["layers"][k][key], ref, what=f"{what} d{key}{k}")
     T = sol.terms_host()
+    gp = np.asarray(g.graph_ptr, dtype=np.int64)
     for gi, t in enumerate(terms):
-        assert abs(T[gi, :S].sum() - t["head"].sum()) <= 1e-5 * (np.abs(t["head"]).sum() + g.n * S + 1)
+        # every head's term on its own, against the sum of its summands' magnitudes
+        lo, hi = int(gp[gi]), int(gp[gi + 1])
+        sub = oobj._slice_graph(g, lo, hi) if gp.size > 2 else g
+        scale = _head_scale(Zo[lo:hi], sub, problem, lam) + 1e-30
+        for s in range(S):
+            assert_close_scalar(T[gi, s], t["head"][s], scale[s], what=f"{what} l_{s} graph {gi}")
+        assert_close_scalar(T[gi, S], t["entropy"], abs(t["entropy"]) + 1e-30, what=f"{what} S(P)")
+        assert_close_scalar(T[gi, S + 1], t["psi"], abs(t["psi"]) + 1e-30, what=f"{what} Psi")
     ev = sol.evaluate()
     Xo = oev.round_solutions(Zo)
     ref_ev = oev.evaluate(Xo, g, problem)

@@ -255,6 +255,56 @@ def test_loss_fwd_bwd(case):
     assert torch.equal(dZ2, dZ) and torch.equal(terms2, terms)
 
 
+IDENTICAL_CASES = [("rrg3_100", 7, "mis", 0), ("rrg20_500", 32, "maxcut", 0),
+                   ("batch", 100, "mis", 1), ("weighted_er_400", 64, "maxcut", 1)]
+
+
+@pytest.mark.parametrize("gname,S,problem,ddof", IDENTICAL_CASES)
+def test_loss_identical_heads_have_zero_psi_gradient(gname, S, problem, ddof):
+    """Nodes whose heads all coincide (a fifth of the rows, non-dyadic values) with
+    nu > 0: sigma_i = 0 there, so the diversity term adds nothing to their gradient --
+    dZ on those rows equals, bit for bit, the nu = 0 result -- and the rest matches
+    the oracle."""
+    a = api()
+    g = GRAPHS[gname]()
+    say(f"identical heads {gname} S={S} {problem} ddof={ddof}")
+    dg = a.DeviceGraph.from_csr(g)
+    Z = random_logits(g.n, S, seed=S + 17)
+    same = np.zeros(g.n, dtype=bool)
+    same[::5] = True
+    Z[same] = Z[same, :1]  # all heads equal on these rows
+    lam = np.logspace(-1, 1, S).astype(np.float32)
+    lam_d = to_dev(lam) if problem == "mis" else None
+    pid = a.MIS if problem == "mis" else a.MAXCUT
+    gamma, nu = -0.6, 0.4
+    Zd = to_dev(Z)
+    out = {}
+    for v in (nu, 0.0):
+        cfg = a.make_loss_cfg(pid, S, lam_d, 2, gamma, v, ddof)
+        ws = torch.empty(a.loss_workspace_bytes(dg, cfg), dtype=torch.uint8, device="cuda")
+        dZ = torch.empty_like(Zd)
+        terms = torch.empty((dg.n_graphs, S + 2), dtype=torch.float64, device="cuda")
+        a.loss_fwd_bwd(dg, cfg, Zd, dZ, terms, ws)
+        torch.cuda.synchronize()
+        out[v] = (dZ.cpu().numpy(), terms.cpu().numpy())
+    dZn, Tn = out[nu]
+    dZ0, _ = out[0.0]
+    assert np.array_equal(dZn[same], dZ0[same]), "diversity gradient on rows with identical heads"
+    assert not np.array_equal(dZn[~same], dZ0[~same])
+    Z64 = Z.astype(np.float64)
+    gp = g.graph_ptr
+    lam64 = lam.astype(np.float64)
+    for gi in range(len(gp) - 1):
+        lo, hi = int(gp[gi]), int(gp[gi + 1])
+        if hi == lo:
+            continue
+        sub = oobj._slice_graph(g, lo, hi) if len(gp) > 2 else g
+        ref = oobj.loss_terms(Z64[lo:hi], sub, problem, lam64, gamma, 2, nu, ddof)
+        assert_close_scalar(Tn[gi, S + 1], ref["psi"], abs(ref["psi"]) + 1e-30, what="Psi")
+        gref = oobj.grad_wrt_Z(Z64[lo:hi], sub, problem, lam64, gamma, 2, nu, ddof)
+        assert_close_array(dZn[lo:hi], gref, what=f"dZ graph {gi}")
+
+
 def test_loss_device_schedule_matches_host_gamma():
     a = api()
     g = GRAPHS["rrg3_100"]()
@@ -334,6 +384,31 @@ def test_round_eval_bit_exact(gname, S, problem):
             np.testing.assert_allclose(wv[gi * S:(gi + 1) * S], e["cut"], rtol=1e-12)
 
 
+def test_round_eval_tiny_and_subnormal_logits():
+    """Rounding at P > 1/2 is Z > 0 exactly: tiny positive and subnormal logits round to
+    1, zeros of either sign and negative values to 0, as the oracle rounds them."""
+    a = api()
+    g = GRAPHS["rrg3_100"]()
+    dg = a.DeviceGraph.from_csr(g)
+    S = 12
+    vals = np.array([0.0, -0.0, 1e-45, -1e-45, 1e-40, 1e-38, 1e-20, 1e-17, 1e-16, 2e-16, -1e-16,
+                     3.0], dtype=np.float32)
+    rng = np.random.default_rng(4)
+    Z = vals[rng.integers(0, vals.size, size=(g.n, S))]
+    Zd = to_dev(Z)
+    X = torch.empty((g.n, S), dtype=torch.uint8, device="cuda")
+    val = torch.empty(S, dtype=torch.int64, device="cuda")
+    vio = torch.empty(S, dtype=torch.int64, device="cuda")
+    a.round_eval(dg, a.MIS, Zd, X, val, vio)
+    torch.cuda.synchronize()
+    Xo = oev.round_solutions(Z.astype(np.float64))
+    assert np.array_equal(X.cpu().numpy(), Xo)
+    assert Xo[Z > 0].all() and not Xo[Z <= 0].any()
+    e = oev.evaluate_one(Xo, g, "mis")
+    assert np.array_equal(val.cpu().numpy(), e["size"])
+    assert np.array_equal(vio.cpu().numpy(), e["violations"])
+
+
 N_GEMM_CFGS = 20  # tile configurations the library's tuner chooses from
 
 
@@ -364,6 +439,30 @@ def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
             ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
             ref = np.maximum(ref + bias, 0.0)
             assert_close_array(C.cpu().numpy(), ref, 2e-6, f"cfg {cfg} {key} splits {splits}")
+    finally:
+        a.autotune_reset()
+
+
+@pytest.mark.parametrize("M,cfg,splits", [(32, 16, 1024), (64, 11, 512)])
+def test_gemm_committed_large_split_plans(M, cfg, splits):
+    """The split-K plans of the committed 256-graph tuning table at their real shape:
+    weight gradients A^T B over K = 710,241 rows in 1,024 and 512 splits, summed in a
+    fixed order, with the bias gradient (column sums of A) beside them."""
+    a = api()
+    N, K = 64, 710241
+    rng = np.random.default_rng(M)
+    A = rng.standard_normal((K, M)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    key = f"TN|{M}x{N}x{K}"
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    try:
+        a.autotune_reset()
+        a.autotune_set(key, cfg, splits)
+        C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+        a.gemm(to_dev(A), to_dev(B), C, True, False, ws=ws)
+        torch.cuda.synchronize()
+        ref = A.astype(np.float64).T @ B.astype(np.float64)
+        assert_close_array(C.cpu().numpy(), ref, 2e-6, f"{key} cfg {cfg} splits {splits}")
     finally:
         a.autotune_reset()
 

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import assert_close_array, assert_close_scalar, assert_update_close, need_gpu, say, to_dev
+from helpers import (assert_close_array, assert_close_scalar, assert_update_close, check_relu_decisions,
+                     need_gpu, say, to_dev)
 from oracle import evaluate as oev
 from oracle import exact as oexact
 from oracle import gnn as ognn
@@ -203,6 +204,159 @@ def test_autograd_function_matches_backward():
     assert_close_array(gg["layers"][1]["Wn"], go["layers"][1]["Wn"], what="autograd dWn1")
 
 
+@pytest.mark.parametrize("kind", ["node_weights", "per_head_node_weights", "instances"])
+def test_autograd_function_uses_the_solvers_objective(kind):
+    """CPRALoss on a weighted-MIS solver (node weights per node or per head) and on a
+    solver with one instance per head (per-head edge weights, MaxCut): R, dZ and the
+    parameter gradients follow that solver's objective, as the training step does."""
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.autograd import CPRALoss
+    from workloads import instance_edge_weights
+    g = random_regular_graph(240, 4, 12)
+    dg = api.DeviceGraph.from_csr(g)
+    S = 8
+    rng = np.random.default_rng(3)
+    nw = ew = None
+    if kind == "instances":
+        problem, lam = "maxcut", None
+        ew = instance_edge_weights(g, S, 5, "uniform", 0.2)
+    else:
+        problem, lam = "mis", np.linspace(0.5, 3, S).astype(np.float32)
+        nw = rng.uniform(0, 1, (g.n, S) if kind == "per_head_node_weights" else g.n).astype(np.float32)
+    cfg = CPRAConfig(problem=problem, layer_kind="sage", n_layers=2, hidden=16, S=S, nu=0.1)
+    sol = CPRASolver(dg, cfg, lam, node_weight=nw, edge_weight=ew)
+    p = init_params("sage", g.n, 2, 16, S, seed=4)
+    sol.load_params(p)
+    gamma = -0.7
+    params = sol.params.clone().requires_grad_(True)
+    R = CPRALoss.apply(params, sol, gamma)
+    assert R.is_cuda and R.dtype == torch.float64
+    R.backward()
+    M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
+    ocfg = otrain.StepConfig(problem=problem, lam=None if lam is None else lam.astype(np.float64),
+                             nu=0.1, node_weight=nw, edge_weight=ew)
+    Zo, terms, dZo, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, gamma)
+    t = terms[0]
+    scale = np.abs(t["head"]).sum() + abs(gamma) * t["entropy"] + 0.1 * abs(t["psi"]) + g.n * S
+    assert_close_scalar(float(R.detach()), t["total"], scale, what=f"{kind} R")
+    assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what=f"{kind} dZ")
+    gg = sol.unpack(params.grad)
+    assert_close_array(gg["emb"], go["emb"], what=f"{kind} d emb")
+    for k in range(2):
+        for key in go["layers"][k]:
+            assert_close_array(gg["layers"][k][key], go["layers"][k][key], what=f"{kind} d{key}{k}")
+    # the plain objective differs: the weights really entered the loss
+    plain = otrain.loss_and_grads(ognn.to_f64(p), M, g, otrain.StepConfig(
+        problem=problem, lam=ocfg.lam, nu=0.1), gamma)[1][0]["total"]
+    assert abs(plain - t["total"]) > 1e-3 * scale
+    sol.close()
+
+
+ES_CASES = [("absolute", 1e-5, 20, False), ("relative", 1e-3, 10, True)]
+
+
+@pytest.mark.parametrize("name,tol,patience,relative", ES_CASES, ids=[c[0] for c in ES_CASES])
+def test_early_stopping_on_device_matches_the_rule(name, tol, patience, relative):
+    """The device's stopping rule against the oracle's rule recomputed on the GPU's own
+    loss history (the head losses and annealing terms the steps wrote): same stopping
+    step; once stopped, further steps change neither the parameters, the Adam moments
+    nor the step counter; a replayed run that polls the flag every 25 steps stops at
+    the same step with the same parameters, bit for bit."""
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.solver import gamma_schedule
+    g = random_regular_graph(200, 3, 21)
+    dg = api.DeviceGraph.from_csr(g)
+    S = 8
+    lam = np.linspace(0.5, 3, S).astype(np.float32)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=16, S=S, T=150,
+                     gamma_start=-2.0, gamma_end=0.5, lr=1e-2)
+    p = init_params("gcn", g.n, 2, 16, S, seed=9)
+    a = CPRASolver(dg, cfg, lam)
+    a.load_params(p)
+    a.enable_early_stopping(tol, patience, relative)
+    head, phi = [], []
+    max_steps = 4000
+    for t in range(max_steps):
+        a.step()
+        T = a.terms_host()
+        head.append(float(T[:, :S].sum()))
+        phi.append(float(np.float64(gamma_schedule(t, cfg.T, cfg.gamma_start, cfg.gamma_end))
+                         * T[:, S].sum()))
+        if a.early_stop_state()["stopped"]:
+            break
+    expected = otrain.early_stop_step(head, phi, tol, patience, relative)
+    st = a.early_stop_state()
+    say(f"  {name}: rule fires at step {expected}; device {st}")
+    assert expected is not None and st["stopped"] == 1
+    assert st["stop_step"] == expected == len(head) - 1
+    assert int(a.step_counter.item()) == expected
+    frozen = [x.clone() for x in (a.params, a.m, a.v)]
+    for _ in range(3):
+        a.step()
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(frozen, (a.params, a.m, a.v)))
+    assert int(a.step_counter.item()) == expected
+    b = CPRASolver(dg, cfg, lam)
+    b.load_params(p)
+    b.enable_early_stopping(tol, patience, relative)
+    n, stop = b.run_with_early_stopping(max_steps, check_every=25)
+    assert stop == expected and n >= expected + 1 and n - (expected + 1) < 25
+    assert torch.equal(b.params, a.params)
+    a.close()
+    b.close()
+
+
+def test_early_stopping_rejects_a_step_without_terms_or_counter():
+    api, CPRAConfig, CPRASolver = mods()
+    g = random_regular_graph(50, 3, 2)
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=8, S=4)
+    sol = CPRASolver(dg, cfg, np.ones(4, np.float32))
+    sol.enable_early_stopping(1e-5, 10)
+    with pytest.raises(api.CpraError):
+        api.train_step(sol.graph, sol.step_cfg, sol.params, sol.grads, sol.m, sol.v, sol.Z, sol.dZ,
+                       None, sol.ws, 1, sol.step_counter)
+    with pytest.raises(api.CpraError):
+        api.train_step(sol.graph, sol.step_cfg, sol.params, sol.grads, sol.m, sol.v, sol.Z, sol.dZ,
+                       sol.terms, sol.ws, 1, None)
+    sol.step_cfg.early_stop.patience = 0
+    with pytest.raises(api.CpraError):
+        sol.step()
+    sol.close()
+
+
+def test_run_until_binary_stops_at_the_first_check_below_eps():
+    """run_until_binary replays in chunks and stops at the first chunk boundary where
+    the annealing term per entry S(P) / (N S) is below eps: the same boundary as a
+    run that reads the terms at every boundary itself."""
+    api, CPRAConfig, CPRASolver = mods()
+    g = random_regular_graph(300, 3, 5)
+    dg = api.DeviceGraph.from_csr(g)
+    S = 6
+    lam = np.linspace(0.5, 3, S).astype(np.float32)
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=16, S=S, T=200,
+                     gamma_start=-2.0, gamma_end=1.0, lr=1e-2)
+    p = init_params("gcn", g.n, 2, 16, S, seed=13)
+    eps, K, steps = 1e-3, 50, 3000
+    a = CPRASolver(dg, cfg, lam)
+    a.load_params(p)
+    n = a.run_until_binary(steps, eps=eps, check_every=K)
+    b = CPRASolver(dg, cfg, lam)
+    b.load_params(p)
+    done, expect = 0, steps
+    while done < steps:
+        b.replay(K)
+        done += K
+        if float(b.terms_host()[:, S].sum()) / (g.n * S) < eps:
+            expect = done
+            break
+    say(f"  run_until_binary stopped after {n} steps (reference {expect})")
+    assert n == expect < steps
+    assert torch.equal(a.params, b.params)
+    a.close()
+    b.close()
+
+
 def test_c1_end_to_end_against_oracle_and_exact_optimum():
     api, CPRAConfig, CPRASolver = mods()
     pr = get_preset("C1")
@@ -365,8 +519,10 @@ def test_train_step_teacher_forced_late_steps(t_at):
     gamma = gamma_schedule(t, cfg.T, cfg.gamma_start, cfg.gamma_end)
     M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
     ocfg = otrain.StepConfig(problem="mis", lam=pr.lam.astype(np.float64), lr=pr.lr)
-    Zo, terms_o, dZo, go = otrain.loss_and_grads(ognn.to_f64(p_before), M, g, ocfg, gamma,
-                                                 relu_active=sol.relu_active())
+    active = sol.relu_active()
+    Zo, terms_o, dZo, go, cache = otrain.loss_and_grads(ognn.to_f64(p_before), M, g, ocfg, gamma,
+                                                        relu_active=active, return_cache=True)
+    check_relu_decisions(active, [c["Y"] for c in cache[: len(active)]], f"t={t}")
     say(f"t={t}: gamma={gamma:.4f}, max |Z|={np.abs(Zo).max():.1f}")
     assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what=f"[{t}] Z")
     assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what=f"[{t}] dZ")

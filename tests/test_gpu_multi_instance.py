@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import assert_close_array, assert_close_scalar, need_gpu, say, to_dev
+from helpers import assert_close_array, assert_close_scalar, check_relu_decisions, need_gpu, say, to_dev
 from oracle import evaluate as oev
 from oracle import gnn as ognn
 from oracle import objective as oobj
@@ -215,8 +215,10 @@ def test_multi_instance_train_step_matches_oracle(case):
     M = ognn.mean_aggregation_matrix(g.row_ptr, g.col_idx)
     ocfg = otrain.StepConfig(problem=problem, lam=None if lam is None else lam.astype(np.float64),
                              nu=nu, edge_weight=ew)
-    Zo, terms_o, dZo, go = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, cfg.gamma_start,
-                                                 relu_active=sol.relu_active())
+    active = sol.relu_active()
+    Zo, terms_o, dZo, go, cache = otrain.loss_and_grads(ognn.to_f64(p), M, g, ocfg, cfg.gamma_start,
+                                                        relu_active=active, return_cache=True)
+    check_relu_decisions(active, [c["Y"] for c in cache[: len(active)]], "instances")
     assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what="Z")
     assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what="dZ")
     gg = sol.unpack(sol.grads)

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import assert_close_array, assert_close_scalar, assert_update_close, need_gpu, say, \
-    to_dev
+from helpers import assert_close_array, assert_close_scalar, assert_update_close, check_relu_decisions, \
+    need_gpu, say, to_dev
 from oracle import gnn as ognn
 from oracle import train as otrain
 from workloads import CSRGraph, disjoint_union, erdos_renyi_graph, init_params_per_graph, \
@@ -48,6 +48,24 @@ def ragged_batch(with_edges=True):
 def graph_rows(g):
     gp = np.asarray(g.graph_ptr, dtype=np.int64)
     return [(int(gp[b]), int(gp[b + 1])) for b in range(gp.size - 1)]
+
+
+def per_graph_preacts(p64, g, n_hidden):
+    """The FP64 pre-activations of the hidden layers, graph by graph (each graph
+    its own network), stacked in the batch's row order."""
+    out = [np.zeros((g.n, 0))] * n_hidden
+    parts = [[] for _ in range(n_hidden)]
+    for b, (lo, hi) in enumerate(graph_rows(g)):
+        if hi == lo:
+            continue
+        sub = otrain.objective._slice_graph(g, lo, hi)
+        M = ognn.mean_aggregation_matrix(sub.row_ptr, sub.col_idx)
+        _, cache = ognn.forward(otrain.graph_params(p64, b, lo, hi), M)
+        for k in range(n_hidden):
+            parts[k].append(cache[k]["Y"])
+    for k in range(n_hidden):
+        out[k] = np.vstack(parts[k])
+    return out
 
 
 @pytest.mark.parametrize("cfg", range(N_GEMM_CFGS))
@@ -161,8 +179,11 @@ def test_per_graph_train_step_matches_oracle(case):
         sol.step()
         torch.cuda.synchronize()
         gamma = gamma_schedule(t, cfg.T, cfg.gamma_start, cfg.gamma_end)
+        active = sol.relu_active()
+        check_relu_decisions(active, per_graph_preacts(ognn.to_f64(p_before), g, len(active)),
+                             f"t={t}")
         Zo, terms_o, dZo, go = otrain.loss_and_grads_per_graph(
-            ognn.to_f64(p_before), g, ocfg, gamma, relu_active=sol.relu_active())
+            ognn.to_f64(p_before), g, ocfg, gamma, relu_active=active)
         assert_close_array(sol.Z.cpu().numpy()[: g.n], Zo, what=f"[{t}] Z")
         assert_close_array(sol.dZ.cpu().numpy()[: g.n], dZo, what=f"[{t}] dZ")
         T_gpu = sol.terms.cpu().numpy()
@@ -219,6 +240,8 @@ def test_per_graph_forward_and_standalone_backward():
         M = ognn.mean_aggregation_matrix(sub.row_ptr, sub.col_idx)
         pb = otrain.graph_params(p64, b, lo, hi)
         Zo, cache = ognn.forward(pb, M)
+        check_relu_decisions([r[lo:hi] for r in relu], [c["Y"] for c in cache[: len(relu)]],
+                             f"graph {b}")
         assert_close_array(Z[lo:hi], Zo, what=f"Z graph {b}")
         go = ognn.backward(pb, M, cache, dZ[lo:hi].astype(np.float64), [r[lo:hi] for r in relu])
         assert_close_array(gg["emb"][lo:hi], go["emb"], what=f"d emb graph {b}")

@@ -515,6 +515,51 @@ def test_first_adam_step_moves_by_lr_times_sign():
     np.testing.assert_allclose(theta, [0.9, -1.9, 2.9], atol=1e-6)
 
 
+def test_early_stop_rule_special_cases():
+    """The stopping rule on sequences whose answer is fixed by hand: constant
+    values stall from step 1 on; a loss that keeps falling by more than the
+    tolerance never stops; a fall inside the tolerance, or any rise, counts as
+    stalled; one monitored value falling is enough to reset the count."""
+    es = lambda h, p, tol, pat: train.early_stop_step(h, p, tol, pat, relative=True)  # noqa: E731
+    const = [5.0] * 30
+    assert es(const, const, 1e-5, 10) == 10
+    assert es(const, const, 1e-5, 1) == 1
+    assert es(const[:10], const[:10], 1e-5, 10) is None
+    falling = [100.0 * 0.99 ** t for t in range(200)]  # 1% per step > tol
+    flat = [5.0] * len(falling)
+    assert es(falling, flat, 1e-3, 5) is None
+    assert es(flat, falling, 1e-3, 5) is None
+    slow = [100.0 * (1 - 1e-6) ** t for t in range(50)]  # falls by 1e-6 < tol = 1e-5
+    assert es(slow, slow, 1e-5, 20) == 20
+    rising = [float(t) for t in range(50)]
+    assert es(rising, rising, 0.0, 3) == 3
+    # steps 1-5 stall, the loss falls at step 6 (reset), steps 7-12 stall: fires at 12
+    L = [1.0] * 6 + [0.5] * 30
+    assert es(L, [2.0] * 36, 1e-5, 6) == 12
+    assert es(L, [2.0] * 36, 1e-5, 5) == 5
+    # negative values: "falling" means moving towards -inf
+    neg = [-1.0 - 0.01 * t for t in range(40)]
+    assert es(neg, [-3.0] * 40, 1e-3, 4) is None
+    assert es([-1.0] * 40, [-3.0] * 40, 1e-3, 4) == 4
+
+
+def test_early_stop_rule_absolute_tolerance():
+    """The paper's plain (absolute) tolerance: a fall of 1e-6 per step is within a
+    tolerance of 1e-5 whatever the values' magnitude; 1e-4 is not; and a value
+    that decays towards 0 geometrically stalls once its steps drop below tol."""
+    es = train.early_stop_step
+    small_fall = [1e6 - 1e-6 * t for t in range(40)]
+    big_fall = [1.0 - 1e-4 * t for t in range(40)]
+    flat = [0.0] * 40
+    assert es(small_fall, flat, 1e-5, 10) == 10
+    assert es(big_fall, flat, 1e-5, 10) is None
+    decay = [0.5 ** t for t in range(60)]  # step t falls by 0.5^t: <= 1e-5 from t = 17 on
+    first = next(t for t in range(1, 60) if decay[t - 1] - decay[t] <= 1e-5)
+    assert first == 17
+    assert es(flat, decay, 1e-5, 8) == first + 7
+    assert es(flat, decay, 1e-5, 8, relative=True) is None  # halves every step: never stalls
+
+
 def test_gamma_schedule_endpoints():
     assert train.gamma_at(0, 2000, -2.0, 0.1) == -2.0
     assert train.gamma_at(1999, 2000, -2.0, 0.1) == pytest.approx(0.1)
