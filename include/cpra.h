@@ -228,6 +228,25 @@ cpra_status cpra_loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg,
                               float* dZ, int64_t lddz, double* terms,
                               void* ws, size_t ws_bytes, cpra_stream_t stream);
 
+/* The fused loss that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): cpra_loss_fwd_bwd with its workspace (the item
+ * table, the per-item partials and, when P is NULL, P = sigmoid(Z)) in a static
+ * device array of CPRA_LOSS_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  Arguments, results and errors
+ * as cpra_loss_fwd_bwd, plus CPRA_ERR_WORKSPACE when this graph and S need
+ * more scratch than the array holds (cpra_loss_workspace_bytes with P NULL;
+ * with P given the P area is not needed).  Every call on a GPU shares that
+ * GPU's array and leaves its contents to the next call: calls ordered on one
+ * stream are safe, calls that overlap in time on one GPU (other streams or
+ * threads) race.  The first call on a device looks up the array's address
+ * there (hipGetSymbolAddress; no allocation). */
+#define CPRA_LOSS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+cpra_status cpra_loss_fwd_bwd_noalloc(const cpra_csr* g, const cpra_loss_cfg* cfg,
+                                      const float* Z, int64_t ldz, const float* P, int64_t ldp,
+                                      float* dZ, int64_t lddz, double* terms,
+                                      cpra_stream_t stream);
+
 /* The total relaxed loss R of Sec. 3.1 / 3.3 from the per-graph terms that
  * cpra_loss_fwd_bwd writes: R = sum_g (sum_s terms[g][s] + gamma * terms[g][S]
  * + nu * terms[g][S+1]), summed in FP64 on the device in a fixed order (heads

@@ -85,6 +85,8 @@ PCsr, PLoss, PModel, PAdam, PStep = (C.POINTER(Csr), C.POINTER(LossCfg), C.POINT
                                      C.POINTER(AdamCfg), C.POINTER(StepCfg))
 
 # name -> (restype, argtypes); restype None means cpra_status (checked)
+LOSS_NOALLOC_SCRATCH_BYTES = 32 << 20  # CPRA_LOSS_NOALLOC_SCRATCH_BYTES
+
 PROTOTYPES = {
     "cpra_abi_version": (I32, []),
     "cpra_status_string": (C.c_char_p, [I32]),
@@ -100,6 +102,7 @@ PROTOTYPES = {
                                  P, I64, P, I64, I32, P, SZ, P]),
     "cpra_loss_workspace_bytes": (SZ, [PCsr, PLoss]),
     "cpra_loss_fwd_bwd": (None, [PCsr, PLoss, P, I64, P, I64, P, I64, P, P, SZ, P]),
+    "cpra_loss_fwd_bwd_noalloc": (None, [PCsr, PLoss, P, I64, P, I64, P, I64, P, P]),
     "cpra_loss_total": (None, [I32, I32, P, C.c_double, C.c_double, P, P]),
     "cpra_sigmoid": (None, [I32, I32, P, I64, P, I64, P]),
     "cpra_model_param_count": (I64, [PModel, I32]),

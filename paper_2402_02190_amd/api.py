@@ -227,6 +227,16 @@ def loss_fwd_bwd(g, cfg: LossCfg, Z: torch.Tensor, dZ: Optional[torch.Tensor],
          _ptr(terms), _ptr(ws), ws.numel(), _stream(stream))
 
 
+def loss_fwd_bwd_noalloc(g, cfg: LossCfg, Z: torch.Tensor, dZ: Optional[torch.Tensor],
+                         terms: Optional[torch.Tensor], P: Optional[torch.Tensor] = None,
+                         stream=None):
+    """cpra_loss_fwd_bwd with its workspace in the library's static device scratch
+    (no allocation; calls that overlap in time on one GPU race)."""
+    call("cpra_loss_fwd_bwd_noalloc", _csr(g), C.byref(cfg), _ptr(Z), Z.stride(0), _ptr(P),
+         0 if P is None else P.stride(0), _ptr(dZ), 0 if dZ is None else dZ.stride(0),
+         _ptr(terms), _stream(stream))
+
+
 def loss_total(terms: torch.Tensor, gamma: float, nu: float, R: torch.Tensor, stream=None):
     """R (device, one float64) = the total loss from the per-graph terms [n_graphs, S+2]."""
     G, S2 = terms.shape

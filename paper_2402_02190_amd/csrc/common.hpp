@@ -36,6 +36,15 @@ void clear_error();
 
 // Brackets one kernel launch with timing events while profiling is on
 // (see profile.hip); `flops` / `bytes` are the launch's algorithmic work.
+// While a ProfSuspend lives on a thread, ProfScope on that thread records
+// nothing (creates no events): for entry points that must not allocate.
+struct ProfSuspend {
+  ProfSuspend();
+  ~ProfSuspend();
+  ProfSuspend(const ProfSuspend&) = delete;
+  ProfSuspend& operator=(const ProfSuspend&) = delete;
+};
+
 class ProfScope {
  public:
   ProfScope(const char* name, hipStream_t stream, double flops, double bytes);

@@ -23,6 +23,7 @@
 // (column, item) and a fixed-order FP64 reduction per graph: deterministic.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -574,6 +575,37 @@ cpra_status loss_terms_reduce(const cpra_csr* g, const cpra_loss_cfg* cfg, doubl
                                advance);
 }
 
+// ---- the workspace of cpra_loss_fwd_bwd_noalloc: one static array per GPU --
+// Host code never passes `scratch` itself (on the host it only names the
+// symbol): the device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[CPRA_LOSS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+cpra_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "loss_fwd_bwd_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    CPRA_FAIL(CPRA_ERR_PARAM, "loss_fwd_bwd_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      CPRA_FAIL(CPRA_ERR_HIP, "loss_fwd_bwd_noalloc: hipGetSymbolAddress on device %d: %s", dev,
+                hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return CPRA_OK;
+}
+}  // namespace
+
 // R = sum_g (sum_s t[g][s] + gamma t[g][S] + nu t[g][S+1]): thread i sums the
 // graphs i, i + 256, ... in order, then a fixed tree over the threads.
 __global__ __launch_bounds__(256) void k_loss_total(int n_graphs, int S, const double* __restrict__ t,
@@ -629,6 +661,30 @@ cpra_status cpra_loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const
   }
   return cpra::loss_fwd_bwd(g, cfg, Z, ldz, P, ldp, dZ, lddz, terms, ws, ws_bytes,
                             cpra::as_stream(stream));
+}
+
+cpra_status cpra_loss_fwd_bwd_noalloc(const cpra_csr* g, const cpra_loss_cfg* cfg, const float* Z,
+                                      int64_t ldz, const float* P, int64_t ldp, float* dZ,
+                                      int64_t lddz, double* terms, cpra_stream_t stream) {
+  CPRA_CHECK(cpra::check_csr(g, "loss_fwd_bwd_noalloc", false,
+                             cfg && cfg->problem == CPRA_MAXCUT && cfg->edge_weight == nullptr));
+  CPRA_CHECK(cpra::check_loss_cfg(g, cfg));
+  if (g->n_nodes > 0) {
+    if (Z == nullptr) CPRA_FAIL(CPRA_ERR_NULL, "loss_fwd_bwd_noalloc: Z is NULL");
+    if (ldz < cfg->S || (P && ldp < cfg->S) || (dZ && lddz < cfg->S))
+      CPRA_FAIL(CPRA_ERR_SHAPE, "loss_fwd_bwd_noalloc: leading dimension < S");
+  }
+  const size_t need = cpra::loss_workspace_bytes(g, cfg->S, P == nullptr);
+  if (need > CPRA_LOSS_NOALLOC_SCRATCH_BYTES)
+    CPRA_FAIL(CPRA_ERR_WORKSPACE,
+              "loss_fwd_bwd_noalloc: this graph and S need %zu bytes of scratch, the static array "
+              "holds %zu (pass P, or use cpra_loss_fwd_bwd with a workspace)",
+              need, (size_t)CPRA_LOSS_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  CPRA_CHECK(cpra::scratch_address(&ws));
+  cpra::ProfSuspend no_events;  // the profiler would create events
+  return cpra::loss_fwd_bwd(g, cfg, Z, ldz, P, ldp, dZ, lddz, terms, ws,
+                            CPRA_LOSS_NOALLOC_SCRATCH_BYTES, cpra::as_stream(stream));
 }
 
 }  // extern "C"

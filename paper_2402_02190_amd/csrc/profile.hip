@@ -45,11 +45,16 @@ hipEvent_t get_event() {
   return e;
 }
 
+thread_local int t_suspended = 0;
+
 }  // namespace
+
+ProfSuspend::ProfSuspend() { ++t_suspended; }
+ProfSuspend::~ProfSuspend() { --t_suspended; }
 
 ProfScope::ProfScope(const char* name, hipStream_t stream, double flops, double bytes)
     : active_(false), stream_(stream) {
-  if (!g_on) return;
+  if (!g_on || t_suspended) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
