@@ -7,11 +7,13 @@ and Adam over every parameter (embedding included).  Steps are replayed
 from a captured HIP graph; gamma follows the annealing schedule on the
 device, so every timed step is a real training step.
 
-Default workload (the 10,000-node configuration the throughput metric is
-quoted on): MIS on a seeded random 5-regular graph (N = 10,000, 25,000
-edges), 2-layer GraphSAGE with hidden width 256, S = 100 heads with
-lambda_s = logspace(-1, 1, 100), alpha = 2, gamma -2 -> +0.1 over 5000
-steps, Adam lr 1e-3, FP32.  value = S * |E| / seconds per step.
+Default workload (the largest single-graph configuration that one GPU
+runs): MIS on a seeded random 20-regular graph (N = 100,000, 1,000,000
+edges), 3-layer GCN with hidden width 128, S = 64 heads with
+lambda_s = logspace(-1, 1, 64), alpha = 2, gamma -2 -> +0.1, Adam lr 1e-3,
+FP32, layer recomputation on.  value = S * |E| / seconds per step.  The
+10,000-node, 5-regular, GraphSAGE-256, S = 100 configuration is measured
+after it with the same contract and reported under the key "C2".
 
 Besides the JSON line's throughput, the run measures per-kernel durations
 with HIP events (the library's profiler: an event pair around every kernel
@@ -81,7 +83,7 @@ def roofline_entry(name, stats, workload):
     launch / average launch time) and, when a counter record for this kernel
     source and workload exists under profiles/, its measured HBM bytes per launch."""
     from paper_2402_02190_amd.traffic import load_traffic
-    launches, ms, flops, nbytes = stats
+    launches, ms, flops, nbytes, gather = stats
     avg_s = ms / 1e3 / launches
     try:
         traffic = load_traffic(name, workload)
@@ -94,10 +96,18 @@ def roofline_entry(name, stats, workload):
                 "avg_us": avg_s * 1e6, "launches": launches,
                 "work_per_launch": flops / launches, "work_unit": "FLOP", "timing": TIMING}
     achieved = nbytes / launches / avg_s / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-            "avg_us": avg_s * 1e6, "launches": launches,
-            "work_per_launch": nbytes / launches, "work_unit": "B", "timing": TIMING}
+    out = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+           "avg_us": avg_s * 1e6, "launches": launches,
+           "work_per_launch": nbytes / launches, "work_unit": "B", "timing": TIMING}
+    if gather > 0:
+        # the neighbour rows the kernel gathers through the CSR index (4 B per entry and
+        # column): what a sparse product over an expander graph streams, from the
+        # Infinity Cache or HBM, beside the compulsory bytes above
+        g_rate = gather / launches / avg_s / 1e9
+        out["gather"] = {"bytes_per_launch": gather / launches, "achieved": g_rate,
+                         "unit": "GB/s", "frac_of_hbm_peak": g_rate / PEAK_HBM_GBS}
+    return out
 
 
 def default_tuning_file(workload: str):
@@ -199,7 +209,7 @@ def loss_sweep(sizes, S: int = 64, d: int = 20, reps: int = 10):
         row = {"n": n, "nnz": g.nnz, "S": S}
         gather = 4.0 * g.nnz * S
         for name in ("loss_fwd_bwd", "aggregate"):
-            la, ms, _, by = st[name]
+            la, ms, _, by, _ = st[name]
             t = ms / 1e3 / la
             row[name] = {"avg_us": t * 1e6, "compulsory_bytes": by / la,
                          "compulsory_GBps": by / la / t / 1e9,
@@ -219,7 +229,7 @@ def loss_sweep(sizes, S: int = 64, d: int = 20, reps: int = 10):
 WARM_WEIGHTS = os.path.join(ROOT, "paper_2402_02190_amd", "weights", "warmstart_mis_rrg.npz")
 
 
-def time_to_target(seeds=(0, 1), n: int = 50_000, d: int = 5):
+def time_to_target(seeds=(0, 1, 2, 3, 4), n: int = 50_000, d: int = 5):
     """The second half of the metric on the 50,000-node warm-start workload: wall
     time until the best feasible head (decoded every 50 steps) reaches a fraction
     of the plain method's final MIS size, for the plain cold-start run, the
@@ -241,86 +251,48 @@ def time_to_target(seeds=(0, 1), n: int = 50_000, d: int = 5):
                                   "control": s["mean_control_final_over_target"]}}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="C2")
-    ap.add_argument("--per-graph-weights", action="store_true",
-                    help="batched workloads: one network per graph instead of one shared network")
-    ap.add_argument("--instances", default=None, choices=["uniform", "signed", "integer", "unit"],
-                    help="one instance per head: per-head edge weights of this kind on the "
-                         "workload's graph (seeded; see workloads.instance_edge_weights)")
-    ap.add_argument("--instance-drop", type=float, default=0.0,
-                    help="with --instances: fraction of (edge, head) pairs left out")
-    ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-time-to-target", action="store_true")
-    ap.add_argument("--tuning-file", default=None,
-                    help="GEMM tuning table: loaded if it exists, else written after autotuning "
-                         "(default: the committed MI355X table of the workload, if any)")
-    ap.add_argument("--pmc-pass", action="store_true",
-                    help="run only the short sequence the HBM counter passes profile")
-    ap.add_argument("--loss-sweep", type=int, nargs="*", default=None, metavar="N",
-                    help="instead of the step benchmark: time the fused loss kernel and the "
-                         "aggregation alone on near-20-regular graphs of these sizes, S = 64")
-    args = ap.parse_args()
-    if args.loss_sweep is not None:
-        sizes = args.loss_sweep or [100_000, 400_000, 1_000_000, 4_000_000]
-        rows = loss_sweep(sizes)
-        print(json.dumps({"sweep": "loss_fwd_bwd and aggregate, near-20-regular random graphs, S=64",
-                          "peak_hbm_GBps": PEAK_HBM_GBS, "rows": rows}), flush=True)
-        return
-    label = args.workload + ("_pergraph" if args.per_graph_weights else "")
-    if args.tuning_file is None and not args.no_autotune:
-        args.tuning_file = default_tuning_file(label)  # the GEMMs do not depend on the instances
-    if args.instances:
-        label += "_instances"
-    if args.gpus != 1:
-        log("bench.py measures one GPU: the library runs one process on one GPU (a batch of graphs "
-            "would shard at graph boundaries, one share per GPU). Run with --gpus 1.")
-        sys.exit(2)
-    rank = int(os.environ.get("RANK", "0"))
-
+def step_benchmark(workload: str, args, per_graph: bool, instances, instance_drop: float,
+                   tuning_file, profile: bool):
+    """Build the workload, load (or tune) the GEMM plans, replay the captured step
+    args.steps times after args.warmup warm-up steps, and profile eager steps.
+    Returns (result dict without the host-side legs, (pr, g, params, W))."""
     import torch
     from paper_2402_02190_amd import api
 
-    pr, g, params = build_workload(args.workload, args.per_graph_weights)
+    label = workload + ("_pergraph" if per_graph else "") + ("_instances" if instances else "")
+    pr, g, params = build_workload(workload, per_graph)
     W = None
-    if args.instances:
+    if instances:
         from workloads import instance_edge_weights
-        W = instance_edge_weights(g, pr.S, 2025, args.instances, args.instance_drop)
-    sol = make_solver(pr, g, params, args.per_graph_weights, W)
+        W = instance_edge_weights(g, pr.S, 2025, instances, instance_drop)
+    sol = make_solver(pr, g, params, per_graph, W)
     torch.cuda.synchronize()
-    log(f"[bench] params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
+    log(f"[bench] {workload}: params={sol.n_params} workspace={sol.ws.numel() / 2**20:.1f} MiB")
 
     # GEMM tile shapes: load a saved tuning table, or autotune on this workload's
     # shapes (one real training step) and save the table
-    if args.tuning_file and os.path.exists(args.tuning_file):
-        with open(args.tuning_file) as f:
+    api.autotune_reset()
+    if tuning_file and os.path.exists(tuning_file):
+        with open(tuning_file) as f:
             for e in json.load(f):
                 api.autotune_set(e["key"], e["cfg"], e["splits"])
-        log(f"[bench] loaded GEMM tuning table {args.tuning_file}")
+        log(f"[bench] loaded GEMM tuning table {tuning_file}")
     elif not args.no_autotune:
         table = sol.autotune()
         for key, choice, us, hus in table:
             log(f"[bench] autotune {key:40s} -> {choice:26s} {us:8.2f} us (heuristic {hus:8.2f} us)")
-        if args.tuning_file:
-            with open(args.tuning_file, "w") as f:
+        if tuning_file:
+            with open(tuning_file, "w") as f:
                 json.dump(api.autotune_table(), f, indent=1)
     if args.pmc_pass:
         pmc_pass(sol, 5)
         sol.close()
-        return
+        return None, (pr, g, params, W)
     # warm-up: capture once, replay W steps
     sol.capture()
     sol.replay(args.warmup)
     torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} steps done")
+    log(f"[bench] {workload}: warmup {args.warmup} steps done")
 
     # timed region: K replayed steps, synchronised on both sides
     stream = sol._stream
@@ -338,7 +310,8 @@ def main():
     ms_event = ev0.elapsed_time(ev1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     value = pr.S * g.n_edges / (ms_per_step / 1e3)
-    log(f"[bench] {args.steps} steps: {ms_per_step:.4f} ms/step wall ({ms_event:.4f} ms by events)")
+    log(f"[bench] {workload}: {args.steps} steps: {ms_per_step:.4f} ms/step wall "
+        f"({ms_event:.4f} ms by events)")
     terms = sol.terms_host()
     if not np.all(np.isfinite(terms)):
         raise RuntimeError("non-finite loss terms")
@@ -349,19 +322,19 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{pr.name}: {pr.description}"
-                               + ("; one network per graph" if args.per_graph_weights else "")
-                               + (f"; one instance per head ({args.instances} edge weights, "
-                                  f"{args.instance_drop:g} left out)" if args.instances else ""),
+                               + ("; one network per graph" if per_graph else "")
+                               + (f"; one instance per head ({instances} edge weights, "
+                                  f"{instance_drop:g} left out)" if instances else ""),
                    "n_nodes": g.n,
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
-                   "problem": pr.problem, "hip_graph_replay": True,
-                   "per_graph_weights": bool(args.per_graph_weights),
+                   "problem": pr.problem, "recompute": bool(pr.recompute),
+                   "hip_graph_replay": True, "per_graph_weights": bool(per_graph),
                    "autotuned_gemm": not args.no_autotune,
                    "ms_per_step_events": ms_event},
     }
 
-    if not args.no_profile:
+    if profile:
         # per-kernel durations: eager steps with an event pair around every kernel,
         # queued behind a GPU sleep so that the host runs ahead of the GPU and the
         # kernels execute back to back as in the replayed graph, all on one stream
@@ -392,14 +365,80 @@ def main():
         if "loss_fwd_bwd" in stats:
             result["roofline_loss"] = roofline_entry("loss_fwd_bwd", stats["loss_fwd_bwd"], label)
         result["kernels"] = kernels
-        log(f"[bench] dominant kernel {dom}: {json.dumps(result['roofline'])}")
+        log(f"[bench] {workload}: dominant kernel {dom}: {json.dumps(result['roofline'])}")
         for k, v in kernels.items():
             log(f"[bench]   {k:28s} {v['launches']:5d} launches {v['avg_us']:9.2f} us avg "
                 f"{100 * v['share']:5.1f}%")
+    sol.close()
+    api.autotune_reset()
+    return result, (pr, g, params, W)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="C4")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the second measurement (the 10,000-node C2 step) after the C4 one")
+    ap.add_argument("--per-graph-weights", action="store_true",
+                    help="batched workloads: one network per graph instead of one shared network")
+    ap.add_argument("--instances", default=None, choices=["uniform", "signed", "integer", "unit"],
+                    help="one instance per head: per-head edge weights of this kind on the "
+                         "workload's graph (seeded; see workloads.instance_edge_weights)")
+    ap.add_argument("--instance-drop", type=float, default=0.0,
+                    help="with --instances: fraction of (edge, head) pairs left out")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--ttt-seeds", type=int, default=5,
+                    help="seeds of the time-to-target comparison (graphs and initialisations)")
+    ap.add_argument("--tuning-file", default=None,
+                    help="GEMM tuning table: loaded if it exists, else written after autotuning "
+                         "(default: the committed MI355X table of the workload, if any)")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="run only the short sequence the HBM counter passes profile")
+    ap.add_argument("--loss-sweep", type=int, nargs="*", default=None, metavar="N",
+                    help="instead of the step benchmark: time the fused loss kernel and the "
+                         "aggregation alone on near-20-regular graphs of these sizes, S = 64")
+    args = ap.parse_args()
+    if args.loss_sweep is not None:
+        sizes = args.loss_sweep or [100_000, 400_000, 1_000_000, 4_000_000]
+        rows = loss_sweep(sizes)
+        print(json.dumps({"sweep": "loss_fwd_bwd and aggregate, near-20-regular random graphs, S=64",
+                          "peak_hbm_GBps": PEAK_HBM_GBS, "rows": rows}), flush=True)
+        return
+    if args.gpus != 1:
+        log("bench.py measures one GPU: the library runs one process on one GPU (a batch of graphs "
+            "would shard at graph boundaries, one share per GPU). Run with --gpus 1.")
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    tuning = args.tuning_file
+    if tuning is None and not args.no_autotune:
+        # the GEMMs do not depend on the instances
+        tuning = default_tuning_file(args.workload + ("_pergraph" if args.per_graph_weights else ""))
+
+    result, (pr, g, params, W) = step_benchmark(args.workload, args, args.per_graph_weights,
+                                                 args.instances, args.instance_drop, tuning,
+                                                 not args.no_profile)
+    if result is None:
+        return
+
+    if args.workload == "C4" and not (args.no_c2 or args.per_graph_weights or args.instances):
+        # the 10,000-node configuration, same contract (its own committed GEMM plans)
+        c2, _ = step_benchmark("C2", args, False, None, 0.0,
+                               None if args.no_autotune else default_tuning_file("C2"),
+                               not args.no_profile)
+        result["C2"] = {k: c2[k] for k in ("value", "ms_per_step", "config", "roofline",
+                                             "roofline_loss") if k in c2}
 
     if rank == 0 and not args.no_time_to_target:
         log("[bench] time to target: cold vs warm start on the 50,000-node graph ...")
-        ttt = time_to_target()
+        ttt = time_to_target(seeds=tuple(range(args.ttt_seeds)))
         if ttt is not None:
             result["time_to_target"] = ttt
             log(f"[bench] time to target: {json.dumps(ttt['median_seconds_to_fraction'])}")
@@ -410,7 +449,6 @@ def main():
                                               W)
         log(f"[bench] cpu baseline: {result['cpu_baseline']}")
 
-    sol.close()
     if rank == 0:
         print(json.dumps(result), flush=True)
 

@@ -584,7 +584,9 @@ cpra_status cpra_autotune_set(const char* key, int32_t cfg, int32_t splits);
  * being captured are not recorded.  profile_collect waits for the recorded
  * events and adds their times to the per-family summary; profile_end frees
  * the events and returns the number of families; profile_get reads family i:
- * launches, summed event time (ms), summed FLOPs and bytes.  Profiling adds
+ * launches, summed event time (ms), summed FLOPs, compulsory bytes, and the
+ * bytes of rows gathered through an index (neighbour rows of the sparse
+ * products, which caches may serve; 0 for other kernels).  Profiling adds
  * two event records per launch: measurement runs only.  An event pair times
  * the kernel plus any wait for the host to launch it, so keep the GPU queue
  * ahead of the host (e.g. start with a sleep on the stream).
@@ -594,7 +596,7 @@ cpra_status cpra_profile_stop(void);     /* stop recording new launches, keep th
 cpra_status cpra_profile_collect(void);  /* add the recorded events' times to the summary */
 cpra_status cpra_profile_end(int32_t* n_kernels);
 cpra_status cpra_profile_get(int32_t i, char* name, size_t name_len, int64_t* launches,
-                             double* total_ms, double* flops, double* bytes);
+                             double* total_ms, double* flops, double* bytes, double* gather);
 
 #ifdef __cplusplus
 }

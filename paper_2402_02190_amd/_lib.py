@@ -148,7 +148,8 @@ PROTOTYPES = {
     "cpra_profile_collect": (None, []),
     "cpra_profile_end": (None, [C.POINTER(I32)]),
     "cpra_profile_get": (None, [I32, C.c_char_p, SZ, C.POINTER(I64), C.POINTER(C.c_double),
-                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
 }
 
 _lib = None

@@ -484,7 +484,7 @@ def profile_collect() -> None:
 
 def profile_end(collect: bool = True):
     """Stop profiling (collecting the recorded events first unless collect=False);
-    returns {name: (launches, total_ms, flops, bytes)}."""
+    returns {name: (launches, total_ms, flops, bytes, gathered bytes)}."""
     if collect:
         profile_collect()
     n = C.c_int32()
@@ -492,9 +492,10 @@ def profile_end(collect: bool = True):
     out = {}
     for i in range(n.value):
         name = C.create_string_buffer(128)
-        la, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
-        call("cpra_profile_get", i, name, 128, C.byref(la), C.byref(ms), C.byref(fl), C.byref(by))
-        out[name.value.decode()] = (la.value, ms.value, fl.value, by.value)
+        la, ms, fl, by, ga = C.c_int64(), C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        call("cpra_profile_get", i, name, 128, C.byref(la), C.byref(ms), C.byref(fl), C.byref(by),
+             C.byref(ga))
+        out[name.value.decode()] = (la.value, ms.value, fl.value, by.value, ga.value)
     return out
 
 

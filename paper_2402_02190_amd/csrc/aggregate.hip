@@ -182,7 +182,8 @@ cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, 
                              (a.mask ? 1.0 : 0.0) + (a.sig_out ? 1.0 : 0.0)) +
                        4.0 * (double)nnz * (TRANS && a.col_inv_deg ? 2.0 : 1.0) +
                        8.0 * (double)a.n + 4.0;
-  ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes);
+  ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes,
+               4.0 * (double)nnz * a.width);
   switch (nc) {
 #define CPRA_AGG_CASE(NCV)                                                                    \
   case NCV:                                                                                   \

@@ -47,7 +47,9 @@ struct ProfSuspend {
 
 class ProfScope {
  public:
-  ProfScope(const char* name, hipStream_t stream, double flops, double bytes);
+  // gather: bytes of rows gathered through an index (a sparse product's neighbour
+  // rows), which caches may serve; 0 for kernels without gathers
+  ProfScope(const char* name, hipStream_t stream, double flops, double bytes, double gather = 0.0);
   ~ProfScope();
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;

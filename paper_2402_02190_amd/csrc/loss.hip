@@ -524,16 +524,18 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.ld_ew = cfg->ld_edge_weight;
   const bool ph = cfg->edge_weight != nullptr;
   const int blocks = (int)xcd_grid(G.items_cap);
-  // compulsory bytes: Z and P read once, dZ written, CSR (+weights), wdeg, partials
+  // compulsory bytes: Z read once, dZ written, CSR (+weights), wdeg, partials.  The
+  // node's own row of P is a second read of what Z already holds (it saves the
+  // sigmoid), so it is not counted; the neighbour rows of P are gathers.
   const double ns4 = 4.0 * (double)g->n_nodes * S;
-  const double loss_bytes = ns4 * (dZ ? 3.0 : 2.0) +
+  const double loss_bytes = ns4 * (dZ ? 2.0 : 1.0) +
                             4.0 * (double)g->nnz * (g->weight && !ph ? 2.0 : 1.0) +
                             4.0 * (double)g->n_nodes * (cfg->problem == CPRA_MAXCUT && !ph ? 2.0 : 1.0) +
                             (cfg->node_weight ? 4.0 * (double)g->n_nodes *
                                                     (cfg->ld_node_weight ? S : 1) : 0.0) +
                             (ph ? 4.0 * (double)g->nnz * S : 0.0) +
                             4.0 * (double)(S + 2) * G.items_cap;
-  ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes);
+  ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes, 4.0 * (double)g->nnz * S);
   bool launched = true;
 #define CPRA_LOSS_LAUNCH(NCV, VECV)                                                              \
   if (ph) hipLaunchKernelGGL((k_loss<NCV, VECV, true>), dim3(blocks), dim3(256), 0, stream, a);  \

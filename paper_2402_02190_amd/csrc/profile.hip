@@ -19,13 +19,13 @@ namespace {
 struct Rec {
   std::string name;
   hipEvent_t a, b;
-  double flops, bytes;
+  double flops, bytes, gather;
 };
 
 struct Summary {
   std::string name;
   int64_t launches = 0;
-  double total_ms = 0, flops = 0, bytes = 0;
+  double total_ms = 0, flops = 0, bytes = 0, gather = 0;
 };
 
 std::mutex g_mu;
@@ -52,7 +52,7 @@ thread_local int t_suspended = 0;
 ProfSuspend::ProfSuspend() { ++t_suspended; }
 ProfSuspend::~ProfSuspend() { --t_suspended; }
 
-ProfScope::ProfScope(const char* name, hipStream_t stream, double flops, double bytes)
+ProfScope::ProfScope(const char* name, hipStream_t stream, double flops, double bytes, double gather)
     : active_(false), stream_(stream) {
   if (!g_on || t_suspended) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -61,7 +61,7 @@ ProfScope::ProfScope(const char* name, hipStream_t stream, double flops, double 
   hipEvent_t a = get_event(), b = get_event();
   if (!a || !b) return;
   hipEventRecord(a, stream);
-  g_recs.push_back(Rec{name, a, b, flops, bytes});
+  g_recs.push_back(Rec{name, a, b, flops, bytes, gather});
   idx_ = g_recs.size() - 1;
   active_ = true;
 }
@@ -117,6 +117,7 @@ cpra_status cpra_profile_collect(void) {
     s.total_ms += ms;
     s.flops += r.flops;
     s.bytes += r.bytes;
+    s.gather += r.gather;
   }
   return CPRA_OK;
 }
@@ -135,7 +136,7 @@ cpra_status cpra_profile_end(int32_t* n_kernels) {
 }
 
 cpra_status cpra_profile_get(int32_t i, char* name, size_t name_len, int64_t* launches,
-                             double* total_ms, double* flops, double* bytes) {
+                             double* total_ms, double* flops, double* bytes, double* gather) {
   using namespace cpra;
   std::lock_guard<std::mutex> lk(g_mu);
   if (i < 0 || i >= (int32_t)g_summary.size()) CPRA_FAIL(CPRA_ERR_PARAM, "profile_get: index out of range");
@@ -147,6 +148,7 @@ cpra_status cpra_profile_get(int32_t i, char* name, size_t name_len, int64_t* la
   if (total_ms) *total_ms = s.total_ms;
   if (flops) *flops = s.flops;
   if (bytes) *bytes = s.bytes;
+  if (gather) *gather = s.gather;
   return CPRA_OK;
 }
 
