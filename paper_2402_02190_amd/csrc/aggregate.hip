@@ -7,6 +7,8 @@
 // the row's lanes) and issues a chunk's row gathers together; every gathered
 // row segment is read as contiguous, coalesced vectors.  Sums run in CSR
 // order, so results are deterministic.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace cpra {
@@ -79,6 +81,9 @@ struct AggArgs {
   int64_t ld_sig;
   const float* add2;  // optional second addend [N, width] (ld_add2)
   int64_t ld_add2;
+  int32_t* queue;  // persistent launches: the work queue (kQueueInts counters)
+  int units;       // persistent launches: row blocks of 4 wavefronts
+  int chunk;       // persistent launches: row blocks per dequeue
 };
 
 __device__ inline float sigmoid_of(float z) {
@@ -87,8 +92,9 @@ __device__ inline float sigmoid_of(float z) {
   return z >= 0.0f ? r : e * r;
 }
 
+// Row block `unit` (4 wavefronts of 64/LPR rows each).
 template <int VEC, int NC, bool TRANS>
-__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+__device__ __forceinline__ void agg_unit(const AggArgs& a, int unit) {
   using V = typename Vec<VEC>::T;
   using O = Vec<VEC>;
   const int lane = threadIdx.x & 63;
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   const int sub = lane >> a.lpr_log2;
   const int cl = lane & (lpr - 1);
   const int rpw = 64 >> a.lpr_log2;
-  const int row = (xcd_unit(blockIdx.x, gridDim.x) * 4 + wave) * rpw + sub;
+  const int row = (unit * 4 + wave) * rpw + sub;
   if (row >= a.n) return;
   const int units = a.width / VEC;
 
@@ -170,6 +176,28 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   }
 }
 
+// One block per row block, in XCD order.
+template <int VEC, int NC, bool TRANS>
+__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+  agg_unit<VEC, NC, TRANS>(a, xcd_unit(blockIdx.x, gridDim.x));
+}
+
+// Persistent: at most the resident blocks, each taking row blocks from the queue.
+template <int VEC, int NC, bool TRANS>
+__global__ __launch_bounds__(256) void k_aggregate_persistent(AggArgs a) {
+  __shared__ int s_chunk;
+  const int chunks = (a.units + a.chunk - 1) / a.chunk;
+  for (bool first = true;; first = false) {
+    if (threadIdx.x == 0) s_chunk = queue_next(a.queue, chunks, first);
+    __syncthreads();
+    const int c = s_chunk;
+    if (c < 0) break;  // uniform across the block
+    const int u1 = min(a.units, (c + 1) * a.chunk);
+    for (int u = c * a.chunk; u < u1; ++u) agg_unit<VEC, NC, TRANS>(a, u);
+    __syncthreads();  // s_chunk is rewritten by the next dequeue
+  }
+}
+
 inline bool aligned(const void* p, int bytes) {
   return p == nullptr || (reinterpret_cast<uintptr_t>(p) % bytes) == 0;
 }
@@ -184,10 +212,21 @@ cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, 
                        8.0 * (double)a.n + 4.0;
   ProfScope ps(TRANS ? "aggregate_transposed" : "aggregate", stream, 0.0, bytes,
                4.0 * (double)nnz * a.width);
+  if (a.queue) CPRA_CHECK(zero_queue(a.queue, stream));
   switch (nc) {
-#define CPRA_AGG_CASE(NCV)                                                                    \
-  case NCV:                                                                                   \
-    hipLaunchKernelGGL((k_aggregate<VEC, NCV, TRANS>), dim3(blocks), dim3(256), 0, stream, a); \
+#define CPRA_AGG_CASE(NCV)                                                                     \
+  case NCV:                                                                                    \
+    if (a.queue) {                                                                             \
+      const int cap = resident_blocks(reinterpret_cast<const void*>(                           \
+                                          &k_aggregate_persistent<VEC, NCV, TRANS>), 256);     \
+      AggArgs ap = a;                                                                          \
+      const int grid = std::min(a.units, cap);                                                 \
+      ap.chunk = queue_chunk(a.units, grid);                                                   \
+      hipLaunchKernelGGL((k_aggregate_persistent<VEC, NCV, TRANS>), dim3(grid), dim3(256), 0,  \
+                         stream, ap);                                                          \
+    } else {                                                                                   \
+      hipLaunchKernelGGL((k_aggregate<VEC, NCV, TRANS>), dim3(blocks), dim3(256), 0, stream, a); \
+    }                                                                                          \
     break;
     CPRA_AGG_CASE(1)
     CPRA_AGG_CASE(2)
@@ -207,7 +246,8 @@ cpra_status launch_nc(const AggArgs& a, int nc, int blocks, hipStream_t stream, 
 cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
                       float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
                       bool relu, const float* mask, int64_t ld_mask, hipStream_t stream,
-                      float* sig_out, int64_t ld_sig, const float* add2, int64_t ld_add2) {
+                      float* sig_out, int64_t ld_sig, const float* add2, int64_t ld_add2,
+                      int32_t* queue) {
   if (g->n_nodes == 0 || width == 0) return CPRA_OK;
   int vec = 1;
   for (int v : {4, 2}) {
@@ -235,10 +275,12 @@ cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float*
   int nc = 1;
   while (nc < need) nc <<= 1;
   if (nc > 16) CPRA_FAIL(CPRA_ERR_SHAPE, "aggregate: width %d exceeds 4096", width);
-  AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
-            g->col_inv_deg, X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2};
   int rows_per_block = 4 * (64 / lpr);
-  int blocks = (int)xcd_grid(ceil_div(g->n_nodes, rows_per_block));
+  const int units_rb = (int)ceil_div(g->n_nodes, rows_per_block);
+  int blocks = (int)xcd_grid(units_rb);
+  AggArgs a{g->n_nodes, width, lpr_log2, relu ? 1 : 0, g->row_ptr, g->col_idx, g->inv_deg,
+            g->col_inv_deg, X, ldx, Y, ldy, add, ld_add, bias, mask, ld_mask, sig_out, ld_sig, add2, ld_add2,
+            (queue && persistent_enabled()) ? queue : nullptr, units_rb, 1};
   if (transpose) {
     if (vec == 4) return launch_nc<4, true>(a, nc, blocks, stream, g->nnz);
     if (vec == 2) return launch_nc<2, true>(a, nc, blocks, stream, g->nnz);

@@ -89,6 +89,66 @@ cpra_status launch_item_ptr(const cpra_csr* g, int rows_per_item, int32_t* item_
 __device__ inline int xcd_unit(int b, int grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
 inline int64_t xcd_grid(int64_t units) { return (units + 7) / 8 * 8; }
 
+// ---- persistent launches over a row-block work queue -----------------------
+// A persistent launch runs at most as many blocks as the device holds at once
+// (resident_blocks) over `chunks` chunks of work units (row blocks, or
+// graph-segmented items).  The chunks form 8 queues, queue x holding the x-th
+// contiguous eighth: the hardware deals block b to XCD b % 8, so block b takes
+// the chunks of queue b % 8 -- an XCD works through its own eighth, as in the
+// XCD-ordered launches.  Each block's first chunk is fixed (its rank among the
+// blocks of its XCD), later ones come from the queue's counter, and a block
+// whose queue is empty takes from the other queues, which balances uneven
+// chunks.  A queue is kQueueInts int32 of device memory: 8 counters, each in
+// its own 128-byte line, zeroed on the launch's stream right before the launch
+// (zero_queue).  Every dequeue attempt advances a counter, so each block leaves
+// after at most chunks + 8 attempts.
+constexpr int kQueueStride = 32;  // ints between two counters (128 bytes)
+constexpr int kQueueInts = 8 * kQueueStride;
+bool persistent_enabled();  // CPRA_PERSISTENT=1 in the environment (read at every call)
+cpra_status zero_queue(int32_t* queue, hipStream_t stream);
+// Blocks of `threads` threads of `kernel` that the current device holds at once
+// (compute units x blocks per unit; cached per device and kernel).
+int resident_blocks(const void* kernel, int threads);
+
+struct QueueRange {
+  int lo, n, fixed;  // first chunk, chunks, chunks handed out without the counter
+};
+__device__ inline QueueRange queue_range(int x, int chunks) {
+  const int per = (chunks + 7) >> 3;
+  QueueRange r;
+  r.lo = min(chunks, x * per);
+  r.n = min(chunks, r.lo + per) - r.lo;
+  r.fixed = ((int)gridDim.x - x + 7) >> 3;  // blocks dealt to XCD x
+  return r;
+}
+
+// The calling block's next chunk, or -1 when every queue is empty (one thread
+// of the block calls it; `first` is true on the block's first call).
+__device__ inline int queue_next(int32_t* q, int chunks, bool first) {
+  const int home = blockIdx.x & 7;
+  if (first) {
+    const QueueRange r = queue_range(home, chunks);
+    const int rank = blockIdx.x >> 3;
+    if (rank < r.n) return r.lo + rank;
+  }
+  for (int i = 0; i < 8; ++i) {
+    const int x = (home + i) & 7;
+    const QueueRange r = queue_range(x, chunks);
+    if (r.n <= r.fixed) continue;  // all of it handed out as first chunks
+    int32_t* c = q + x * kQueueStride;
+    if (__atomic_load_n(c, __ATOMIC_RELAXED) >= r.n - r.fixed) continue;  // drained
+    const int t = atomicAdd(c, 1);
+    if (t < r.n - r.fixed) return r.lo + r.fixed + t;
+  }
+  return -1;
+}
+
+// Units per chunk: about four chunks per block of a grid of `grid`.
+inline int queue_chunk(int units, int grid) {
+  const int c = units / (4 * (grid > 0 ? grid : 1));
+  return c > 1 ? c : 1;
+}
+
 __device__ inline bool item_rows(int b, int n_graphs, int n_nodes, const int32_t* graph_ptr,
                                  const int32_t* item_ptr, int R, int* g_out, int* r0, int* r1) {
   if (graph_ptr == nullptr) {
@@ -178,11 +238,14 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs, int n, void
 
 // sig_out (optional) receives sigmoid(Y) with leading dimension ld_sig.
 // add2 (optional) is a second addend [N, width] (ld_add2), applied after add.
+// queue (optional, kQueueInts ints of device memory used by this stream only):
+// with persistent launches enabled, the aggregation runs as a persistent launch
+// over that work queue.
 cpra_status aggregate(const cpra_csr* g, bool transpose, int width, const float* X, int64_t ldx,
                       float* Y, int64_t ldy, const float* add, int64_t ld_add, const float* bias,
                       bool relu, const float* mask, int64_t ld_mask, hipStream_t stream,
                       float* sig_out = nullptr, int64_t ld_sig = 0, const float* add2 = nullptr,
-                      int64_t ld_add2 = 0);
+                      int64_t ld_add2 = 0, int32_t* queue = nullptr);
 
 cpra_status sigmoid(int N, int S, const float* Z, int64_t ldz, float* P, int64_t ldp,
                     hipStream_t stream);

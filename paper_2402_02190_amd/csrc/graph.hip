@@ -1,4 +1,9 @@
 // Graph preparation, graph-segmented fixed-order reductions and small utility kernels.
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "common.hpp"
 
 namespace cpra {
@@ -128,6 +133,41 @@ cpra_status fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t stream) {
   hipLaunchKernelGGL(k_fill_i64, dim3(ceil_div(n, 256)), dim3(256), 0, stream, p, n, v);
   CPRA_CHECK_LAUNCH("fill_i64");
   return CPRA_OK;
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+bool persistent_enabled() {
+  const char* e = getenv("CPRA_PERSISTENT");
+  return e != nullptr && e[0] == '1';
+}
+
+cpra_status zero_queue(int32_t* queue, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, stream, queue, kQueueInts);
+  CPRA_CHECK_LAUNCH("zero_queue");
+  return CPRA_OK;
+}
+
+int resident_blocks(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(dev, kernel);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int n = cus * per_cu;
+  cache[key] = n;
+  return n;
 }
 
 __global__ void k_increment(int32_t* c) {

@@ -58,6 +58,8 @@ struct LossArgs {
   int64_t ld_nw;        // 0: one weight per node
   const float* edge_w;  // per-head edge weights [nnz, ld_ew] (PH) or null
   int64_t ld_ew;
+  int32_t* queue;  // persistent launches: the work queue (kQueueInts counters)
+  int chunk;       // persistent launches: items per dequeue
 };
 
 __device__ inline float wave_sum_xor(float v, int from_mask, int to_mask) {
@@ -89,10 +91,10 @@ struct HV {
 
 // Lane layout: a wavefront holds 64/LPR nodes; lane cl of a node owns NC units
 // of VEC consecutive heads, unit c covering heads (c * LPR + cl) * VEC + e.
+// Item `item` (a block of rows inside one graph) and its partial sums.
 template <int NC, int VEC, bool PH>
-__global__ __launch_bounds__(256) void k_loss(LossArgs a) {
+__device__ __forceinline__ void loss_item(const LossArgs& a, int item) {
   int g, r0, r1;
-  const int item = xcd_unit(blockIdx.x, gridDim.x);
   if (!item_rows(item, a.n_graphs, a.n, a.graph_ptr, a.item_ptr, a.R, &g, &r0, &r1)) return;
 
   float gamma = a.gamma;
@@ -368,6 +370,32 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a) {
   }
 }
 
+// One block per item, in XCD order.
+template <int NC, int VEC, bool PH>
+__global__ __launch_bounds__(256) void k_loss(LossArgs a) {
+  loss_item<NC, VEC, PH>(a, xcd_unit(blockIdx.x, gridDim.x));
+}
+
+// Persistent: at most the resident blocks, each taking items from the queue.  An
+// item's partials do not depend on the block that computes it.
+template <int NC, int VEC, bool PH>
+__global__ __launch_bounds__(256) void k_loss_persistent(LossArgs a) {
+  __shared__ int s_chunk;
+  const int items = (int)a.items_cap;
+  const int chunks = (items + a.chunk - 1) / a.chunk;
+  for (bool first = true;; first = false) {
+    if (threadIdx.x == 0) s_chunk = queue_next(a.queue, chunks, first);
+    __syncthreads();
+    const int c = s_chunk;
+    if (c < 0) break;  // uniform across the block
+    const int i1 = min(items, (c + 1) * a.chunk);
+    for (int it = c * a.chunk; it < i1; ++it) {
+      loss_item<NC, VEC, PH>(a, it);
+      __syncthreads();  // the reduction's LDS is rewritten by the next item
+    }
+  }
+}
+
 // Lanes per node (LPR), units per lane (NC) for VEC heads per unit.
 struct LossLanes {
   int lpr, lpr_log2, nc;
@@ -410,14 +438,16 @@ LossGeom loss_geom(const cpra_csr* g, int S) {
 inline bool al16(const void* p) { return p == nullptr || reinterpret_cast<uintptr_t>(p) % 16 == 0; }
 
 struct LossWs {
-  size_t p_off, item_off, part_off, total;
+  size_t p_off, item_off, part_off, queue_off, total;
 };
 
-// Workspace: [item table][partials][P = sigmoid(Z) when the caller passes none].
+// Workspace: [work queue][item table][partials][P = sigmoid(Z) when the caller passes none].
 LossWs loss_ws_layout(const cpra_csr* g, int S, bool need_p) {
   LossGeom G = loss_geom(g, S);
   LossWs w{};
   size_t off = 0;
+  w.queue_off = off;
+  off += align_up((size_t)kQueueInts * sizeof(int32_t), 256);
   w.item_off = off;
   off += align_up((size_t)(g->n_graphs + 1) * sizeof(int32_t), 256);
   w.part_off = off;
@@ -522,6 +552,7 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
   a.ld_nw = cfg->ld_node_weight;
   a.edge_w = cfg->edge_weight;
   a.ld_ew = cfg->ld_edge_weight;
+  a.queue = persistent_enabled() ? reinterpret_cast<int32_t*>(base + L.queue_off) : nullptr;
   const bool ph = cfg->edge_weight != nullptr;
   const int blocks = (int)xcd_grid(G.items_cap);
   // compulsory bytes: Z read once, dZ written, CSR (+weights), wdeg, partials.  The
@@ -537,9 +568,26 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
                             4.0 * (double)(S + 2) * G.items_cap;
   ProfScope ps("loss_fwd_bwd", stream, 0.0, loss_bytes, 4.0 * (double)g->nnz * S);
   bool launched = true;
-#define CPRA_LOSS_LAUNCH(NCV, VECV)                                                              \
-  if (ph) hipLaunchKernelGGL((k_loss<NCV, VECV, true>), dim3(blocks), dim3(256), 0, stream, a);  \
-  else hipLaunchKernelGGL((k_loss<NCV, VECV, false>), dim3(blocks), dim3(256), 0, stream, a);
+  if (a.queue) CPRA_CHECK(zero_queue(a.queue, stream));
+  // a persistent launch runs min(items, resident blocks) blocks
+  auto pgrid = [&](const void* k) {
+    const int grid = (int)std::min<int64_t>(G.items_cap, resident_blocks(k, 256));
+    a.chunk = queue_chunk((int)G.items_cap, grid);
+    return dim3((unsigned)grid);
+  };
+#define CPRA_LOSS_ONE(NCV, VECV, PHV)                                                               \
+  if (a.queue) {                                                                                    \
+    const dim3 grid = pgrid(reinterpret_cast<const void*>(&k_loss_persistent<NCV, VECV, PHV>));     \
+    hipLaunchKernelGGL((k_loss_persistent<NCV, VECV, PHV>), grid, dim3(256), 0, stream, a);         \
+  } else {                                                                                          \
+    hipLaunchKernelGGL((k_loss<NCV, VECV, PHV>), dim3(blocks), dim3(256), 0, stream, a);            \
+  }
+#define CPRA_LOSS_LAUNCH(NCV, VECV)    \
+  if (ph) {                            \
+    CPRA_LOSS_ONE(NCV, VECV, true)     \
+  } else {                             \
+    CPRA_LOSS_ONE(NCV, VECV, false)    \
+  }
   if (vec4) {
     switch (LN.nc) {
       case 1: CPRA_LOSS_LAUNCH(1, 4) break;
@@ -558,6 +606,7 @@ cpra_status loss_fwd_bwd(const cpra_csr* g, const cpra_loss_cfg* cfg, const floa
     }
   }
 #undef CPRA_LOSS_LAUNCH
+#undef CPRA_LOSS_ONE
   if (!launched) CPRA_FAIL(CPRA_ERR_PARAM, "loss: S too large");
   CPRA_CHECK_LAUNCH("loss");
   if (terms) CPRA_CHECK(loss_terms_reduce(g, cfg, terms, ws, stream));

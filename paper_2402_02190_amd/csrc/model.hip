@@ -67,6 +67,7 @@ struct Plan {
   size_t ax_off[kMaxLayers];  // saved M H of aggregate-first layers
   size_t ax_scratch_off;      // recompute buffer
   size_t yy_off, d_off[2], g_off, t_off[2], p_off, gemm_off, rows_off;
+  size_t q_off;  // work queues of persistent aggregations: [main stream | side stream]
   size_t gemm_bytes;
   size_t total;
 };
@@ -197,12 +198,19 @@ void make_plan(const cpra_model_cfg* cfg, const cpra_csr* g, Plan* p) {
   p->gemm_bytes = gb;
   p->gemm_off = gb ? take(gb) : 0;
   p->rows_off = p->G > 1 ? take(group_rows_bytes(g)) : 0;
+  p->q_off = take(2 * kQueueInts * sizeof(int32_t));
   p->total = std::max<size_t>(off, 256);
 }
 
 inline float* fptr(void* ws, size_t off) {
   return reinterpret_cast<float*>(static_cast<char*>(ws) + off);
 }
+
+// The work queue of the aggregations on the main (0) or side (1) stream.
+inline int32_t* queue_of(void* ws, const Plan& p, int which) {
+  return reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.q_off) + which * kQueueInts;
+}
+
 
 cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, float* Z,
                          int64_t ldz, void* ws, hipStream_t st) {
@@ -227,7 +235,8 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       float* AX = fptr(ws, p.recompute ? p.ax_scratch_off : p.ax_off[k]);
       const bool saved_ax = p.reuse_prefix && k == k0 && !p.recompute;  // M H of a frozen input
       if (!saved_ax)
-        CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st));
+        CPRA_CHECK(aggregate(g, false, l.in, H, ldh, AX, l.in, nullptr, 0, nullptr, false, nullptr, 0, st,
+                             nullptr, 0, nullptr, 0, queue_of(ws, p, 0)));
       GemmProblem q{};
       q.piece[0] = GemmPiece{H, Ws, ldh, l.in, l.in};
       q.piece[1] = GemmPiece{AX, Wn, l.in, l.in, l.in};
@@ -263,7 +272,8 @@ cpra_status forward_impl(const cpra_csr* g, const Plan& p, const float* params, 
       if (p.G > 1) q[0].bias = b;
       CPRA_CHECK(gemm_batch(false, true, q, 2, nullptr, 0, st));
       CPRA_CHECK(aggregate(g, false, l.out, YY + l.out, ldyy, dst, ldd, YY, ldyy, p.G > 1 ? nullptr : b,
-                           !last, nullptr, 0, st, P, l.out, last ? p.z_offset : nullptr, l.out));
+                           !last, nullptr, 0, st, P, l.out, last ? p.z_offset : nullptr, l.out,
+                           queue_of(ws, p, 0)));
     }
     H = dst;
     ldh = ldd;
@@ -354,7 +364,8 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       float* T = fptr(ws, p.t_off[tping]);
       tping ^= 1;
       CPRA_CHECK(before_write(T));
-      CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st));
+      CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st,
+                           nullptr, 0, nullptr, 0, queue_of(ws, p, 0)));
       if (side) {
         CPRA_CHECK(fork_to(side, st));
         CPRA_CHECK(forked());
@@ -396,7 +407,8 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       const float* AX;
       if (p.recompute) {
         float* buf = fptr(ws, p.ax_scratch_off);
-        CPRA_CHECK(aggregate(g, false, l.in, Hk, ldh, buf, l.in, nullptr, 0, nullptr, false, nullptr, 0, wst));
+        CPRA_CHECK(aggregate(g, false, l.in, Hk, ldh, buf, l.in, nullptr, 0, nullptr, false, nullptr, 0, wst,
+                             nullptr, 0, nullptr, 0, queue_of(ws, p, side ? 1 : 0)));
         AX = buf;
       } else {
         AX = fptr(ws, p.ax_off[k]);
@@ -428,7 +440,8 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       }
       CPRA_CHECK(gemm_batch(false, false, r, 2, nullptr, 0, st));
       CPRA_CHECK(before_write(dX));
-      CPRA_CHECK(aggregate(g, true, l.in, G + l.in, ldg, dX, lddx, G, ldg, nullptr, false, mask, ldh, st));
+      CPRA_CHECK(aggregate(g, true, l.in, G + l.in, ldg, dX, lddx, G, ldg, nullptr, false, mask, ldh, st,
+                           nullptr, 0, nullptr, 0, queue_of(ws, p, 0)));
     }
     dY = dX;
     lddy = lddx;

@@ -357,6 +357,36 @@ def test_run_until_binary_stops_at_the_first_check_below_eps():
     b.close()
 
 
+@pytest.mark.parametrize("preset", ["C3s", "C2"])
+def test_persistent_launches_are_bit_identical(preset, monkeypatch):
+    """The persistent aggregation and loss launches (CPRA_PERSISTENT=1: at most the
+    resident blocks, taking row blocks / graph-segmented items from XCD-local work
+    queues) give the same bits as one block per unit: three replayed training steps
+    on the 32-graph ER batch (ragged graphs, per-graph items) and on the 10,000-node
+    graph, and the standalone loss call."""
+    api, CPRAConfig, CPRASolver = mods()
+    pr = get_preset(preset)
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
+                     hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu, T=pr.T)
+    p = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=3)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("CPRA_PERSISTENT", mode)
+        sol = CPRASolver(dg, cfg, pr.lam)
+        sol.load_params(p)
+        sol.run(3, use_graph=True)
+        dZ2 = torch.empty_like(sol.Z)
+        t2 = torch.empty_like(sol.terms)
+        api.loss_fwd_bwd(sol.graph, sol.loss_cfg, sol.Z, dZ2, t2, sol.loss_workspace())
+        torch.cuda.synchronize()
+        out[mode] = [x.clone() for x in (sol.params, sol.Z, sol.dZ, sol.terms, dZ2, t2)]
+        sol.close()
+    for name, x, y in zip(("params", "Z", "dZ", "terms", "loss dZ", "loss terms"), out["0"], out["1"]):
+        assert torch.equal(x, y), name
+
+
 def test_c1_end_to_end_against_oracle_and_exact_optimum():
     api, CPRAConfig, CPRASolver = mods()
     pr = get_preset("C1")
