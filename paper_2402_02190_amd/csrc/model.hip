@@ -33,6 +33,7 @@
 // linear-first order the bias moves into the self-weight GEMM's epilogue
 // (it is graph g's bias for graph g's rows).
 #include <algorithm>
+#include <cstdlib>
 #include <functional>
 
 #include "common.hpp"
@@ -206,6 +207,11 @@ inline float* fptr(void* ws, size_t off) {
   return reinterpret_cast<float*>(static_cast<char*>(ws) + off);
 }
 
+bool wgrad_late() {
+  const char* e = getenv("CPRA_WGRAD_LATE");
+  return e != nullptr && e[0] == '1';
+}
+
 // The work queue of the aggregations on the main (0) or side (1) stream.
 inline int32_t* queue_of(void* ws, const Plan& p, int which) {
   return reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.q_off) + which * kQueueInts;
@@ -366,6 +372,24 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       CPRA_CHECK(before_write(T));
       CPRA_CHECK(aggregate(g, true, l.out, dY, lddy, T, l.out, nullptr, 0, nullptr, false, nullptr, 0, st,
                            nullptr, 0, nullptr, 0, queue_of(ws, p, 0)));
+      // late: the weight gradients fork after dX, so that they run beside the next
+      // layer's gather instead of beside dX's product
+      const bool late = side && wgrad_late() && need_dx && k > p.train_from;
+      if (late) {
+        GemmProblem r{};
+        r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
+        r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
+        r.n_pieces = 2;
+        r.C = dX;
+        r.ldc = lddx;
+        r.M = N;
+        r.N = l.in;
+        r.mask = mask;
+        r.ld_mask = ldh;
+        set_groups(p, g, &rows, 1, &r, l);
+        CPRA_CHECK(before_write(dX));
+        CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
+      }
       if (side) {
         CPRA_CHECK(fork_to(side, st));
         CPRA_CHECK(forked());
@@ -385,6 +409,12 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
       if (!need_dx) break;
+      if (late) {
+        dY = dX;
+        lddy = lddx;
+        ping ^= 1;
+        continue;
+      }
       GemmProblem r{};
       r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
       r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};

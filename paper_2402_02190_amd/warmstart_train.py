@@ -270,11 +270,11 @@ def evaluate(weights: str, n: int = 50_000, degrees: Sequence[int] = (3, 5, 10),
              seeds: Sequence[int] = (0, 1, 2, 3, 4), T: int = 3000, K: int = 50,
              scale: float = 1.0, warm_gamma_start: float = -2.0, warm_T: Optional[int] = None,
              control: bool = True, out: Optional[str] = None, decay_steps: int = 0,
-             fractions: Sequence[float] = (0.9, 0.95, 0.98, 0.99, 1.0)):
+             fractions: Sequence[float] = (0.9, 0.95, 0.98, 0.99, 1.0), extra_steps: int = 0):
     """Arms per graph: cold (plain CPRA, gamma -2 -> 0.1 over T steps); warm
-    (z_offset = scale * Z_w, gamma warm_gamma_start -> 0.1 over warm_T steps);
-    control (the warm arm's schedule without the network).  Target = the cold
-    arm's final best feasible MIS size."""
+    (z_offset = scale * Z_w, gamma warm_gamma_start -> 0.1 over warm_T steps, then
+    extra_steps more at gamma 0.1); control (the warm arm's schedule without the
+    network).  Target = the cold arm's final best feasible MIS size."""
     from workloads import random_channels, random_regular_graph
     net = WarmStartNet.load(weights) if isinstance(weights, str) else weights
     S = net.S
@@ -300,7 +300,8 @@ def evaluate(weights: str, n: int = 50_000, degrees: Sequence[int] = (3, 5, 10),
             warm = Arm(dg, S, warm_T, seed=sd, z_offset=Zw, gamma_start=warm_gamma_start,
                        decay_steps=decay_steps)
             torch.cuda.synchronize()
-            trace_w = [(s_ + t_inf, k, b) for s_, k, b in warm.run(warm_T, K, time.perf_counter())]
+            trace_w = [(s_ + t_inf, k, b) for s_, k, b in warm.run(warm_T + extra_steps, K,
+                                                                    time.perf_counter())]
             warm.sol.close()
             row = {"d": d, "seed": sd, "n": n, "target": target, "warm_inference_s": t_inf,
                    "warm_best_at_0": trace_w[0][2], "warm_final": trace_w[-1][2]}
@@ -311,7 +312,7 @@ def evaluate(weights: str, n: int = 50_000, degrees: Sequence[int] = (3, 5, 10),
             if control:
                 ctl = Arm(dg, S, warm_T, seed=sd, gamma_start=warm_gamma_start)
                 torch.cuda.synchronize()
-                trace_x = ctl.run(warm_T, K, time.perf_counter())
+                trace_x = ctl.run(warm_T + extra_steps, K, time.perf_counter())
                 ctl.sol.close()
                 row["control_time_s"], row["control_steps"] = first_time(trace_x, target)
                 row["control_final"] = trace_x[-1][2]
@@ -346,6 +347,7 @@ def evaluate(weights: str, n: int = 50_000, degrees: Sequence[int] = (3, 5, 10),
                     if any(t is not None for t in ts) else None}
     summ = {"n": n, "degrees": list(degrees), "seeds": list(seeds), "T": T, "K": K, "scale": scale,
             "warm_gamma_start": warm_gamma_start, "warm_T": warm_T, "decay_steps": decay_steps,
+            "extra_steps": extra_steps,
             "curves": curves, "rows": rows,
             "warm_reached": len(reached), "total": len(rows),
             "control_reached": sum(1 for r in rows if r.get("control_time_s") is not None),
