@@ -336,6 +336,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   // outside the matrix is already in the tile).
   constexpr int BG = NT / BM > 0 ? NT / BM : 1;  // threads per row
   static_assert(BK % BG == 0, "bias slice");
+  static_assert(NT >= BM, "every row of the A tile needs a thread for the bias slice");
   const bool do_bias = bgrad_g != nullptr && tn_idx == 0;
   const int b_row = tid % BM, b_grp = tid / BM;
   float bsum = 0.f;
@@ -344,7 +345,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   auto compute = [&](int cur) {
     const float* as = As[cur];
     const float* bs = Bs[cur];
-    if (do_bias && b_grp < BG) {
+    // b_grp < BG for every thread (NT >= BM), so the branch is uniform across the
+    // block: a scalar branch, no exec mask, which keeps the accumulators in place
+    if (do_bias) {
 #pragma unroll
       for (int q = 0; q < BK / BG; ++q) bsum += as[(b_grp * (BK / BG) + q) * TA::LD + b_row];
     }
@@ -394,11 +397,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
     // are unconditional (past the last tile they re-read it, unused) and
     // branch-free, so the compiler can wait for set `nxt` alone while the
     // loads of set `fre` stay in flight.
+    // Pairs of steps run with unconditional MFMAs (a conditional around them
+    // made the compiler copy the accumulators out of and back into the matrix
+    // registers every pair, waiting for the MFMA chain to drain each time); an
+    // odd last step follows the loop.
     TA ta0, ta1;
     TB tb0, tb1;
     auto body = [&](int kt, int cur, TA& fre_a, TB& fre_b, TA& nxt_a, TB& nxt_b) {
       load_into(fre_a, fre_b, min(kt + 2, kt_end - 1));
-      if (kt < kt_end) compute(cur);
+      compute(cur);
       if (kt + 1 < kt_end) {
         nxt_a.store_masked(As[cur ^ 1], tid);
         nxt_b.store_masked(Bs[cur ^ 1], tid);
@@ -411,10 +418,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
       ta0.store_masked(As[0], tid);
       tb0.store_masked(Bs[0], tid);
       __syncthreads();
-      for (int kt = kt_begin; kt < kt_end; kt += 2) {
+      int kt = kt_begin;
+      for (; kt + 1 < kt_end; kt += 2) {
         body(kt, 0, ta0, tb0, ta1, tb1);
         body(kt + 1, 1, ta1, tb1, ta0, tb0);
       }
+      if (kt < kt_end) compute(0);  // odd count: the last tile is in LDS buffer 0
     }
   }
 
