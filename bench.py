@@ -298,16 +298,27 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
     stream = sol._stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # events at the ends of five equal chunks of the K steps (same stream, no sync):
+    # the median chunk is reported beside the K-step figure
+    n_chunks = 5 if args.steps >= 5 else 1
+    bounds = [args.steps * c // n_chunks for c in range(n_chunks + 1)]
+    chunk_ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks - 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
         api.graph_launch(sol._graph, stream)
+        if i + 1 in bounds[1:-1]:
+            chunk_ev[bounds.index(i + 1) - 1].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sol.t += args.steps
     ms_event = ev0.elapsed_time(ev1) / args.steps
+    marks = [ev0] + chunk_ev + [ev1]
+    chunk_ms = sorted(marks[c].elapsed_time(marks[c + 1]) / (bounds[c + 1] - bounds[c])
+                      for c in range(n_chunks))
+    ms_median_chunk = chunk_ms[n_chunks // 2]
     ms_per_step = wall * 1e3 / args.steps
     value = pr.S * g.n_edges / (ms_per_step / 1e3)
     log(f"[bench] {workload}: {args.steps} steps: {ms_per_step:.4f} ms/step wall "
@@ -331,7 +342,8 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
                    "problem": pr.problem, "recompute": bool(pr.recompute),
                    "hip_graph_replay": True, "per_graph_weights": bool(per_graph),
                    "autotuned_gemm": not args.no_autotune,
-                   "ms_per_step_events": ms_event},
+                   "ms_per_step_events": ms_event,
+                   "ms_per_step_median_of_5_chunks": ms_median_chunk},
     }
 
     if profile:

@@ -16,4 +16,4 @@ streams only.
 
 from ._lib import CpraError  # noqa: F401
 from .api import DeviceGraph  # noqa: F401
-from .solver import CPRAConfig, CPRASolver, gamma_schedule  # noqa: F401
+from .solver import CPRAConfig, CPRASolver, SolveResult, gamma_schedule, solve  # noqa: F401

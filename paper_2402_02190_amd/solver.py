@@ -368,3 +368,72 @@ class CPRASolver:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class SolveResult:
+    """What `solve` returns: the rounded heads of the last step and their scores.
+    X [N, S] uint8; value and violations [G, S] int64 (set size or cut per graph and
+    head); wvalue [G, S] float64 with node or edge weights (else None); best_head [G]
+    the best feasible head of each graph (-1: none feasible) and best_value [G] its
+    score (weighted score where there are weights); steps run, the step at which early
+    stopping fired (or None) and the wall time of the training loop in seconds."""
+    X: np.ndarray
+    value: np.ndarray
+    violations: np.ndarray
+    wvalue: Optional[np.ndarray]
+    best_head: np.ndarray
+    best_value: np.ndarray
+    steps: int
+    stop_step: Optional[int]
+    seconds: float
+
+
+def solve(graph, cfg: CPRAConfig, lam=None, params: Optional[Dict[str, object]] = None,
+          seed: int = 0, early_stopping: Optional[Dict[str, object]] = None, device="cuda",
+          **solver_kw) -> SolveResult:
+    """Train CPRA on `graph` (a CSRGraph or a DeviceGraph) for cfg.T steps -- one step
+    captured and replayed (Sec. 3.1 loop) -- then round every head at P > 0.5 and score it.
+    lam: the MIS penalties [S] (default logspace(-1, 1, S)); params: initial parameters
+    (default: seeded `workloads.init_params`, or `init_params_per_graph` with
+    per-graph weights); early_stopping: keyword arguments of
+    `CPRASolver.enable_early_stopping` (tol, patience, relative), or None to train all
+    T steps; solver_kw: z_offset, node_weight, edge_weight of CPRASolver."""
+    import time
+
+    dg = graph if isinstance(graph, DeviceGraph) else DeviceGraph.from_csr(graph, device=device)
+    if lam is None and cfg.problem == "mis":
+        lam = np.logspace(-1.0, 1.0, cfg.S).astype(np.float32)
+    sol = CPRASolver(dg, cfg, lam=lam, device=device, **solver_kw)
+    try:
+        if params is None:
+            from workloads import init_params, init_params_per_graph
+            if cfg.per_graph_weights:
+                params = init_params_per_graph(cfg.layer_kind, dg.n, cfg.n_layers, cfg.hidden,
+                                               cfg.S, dg.n_graphs, seed=seed, in_dim=cfg.in_dim)
+            else:
+                params = init_params(cfg.layer_kind, dg.n, cfg.n_layers, cfg.hidden, cfg.S,
+                                     seed=seed, in_dim=cfg.in_dim)
+        sol.load_params(params)
+        stop_step = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if early_stopping is not None:
+            sol.enable_early_stopping(**early_stopping)
+            steps, stop_step = sol.run_with_early_stopping(cfg.T)
+        else:
+            sol.run(cfg.T)
+            steps = cfg.T
+        sol.forward()  # the logits of the trained parameters
+        ev = sol.evaluate()
+        seconds = time.perf_counter() - t0
+    finally:
+        sol.close()
+    score = ev.get("wvalue", ev["value"]).astype(np.float64)
+    feasible = ev["violations"] == 0
+    masked = np.where(feasible, score, -np.inf)
+    best_head = np.where(feasible.any(axis=1), masked.argmax(axis=1), -1)
+    best_value = np.where(best_head >= 0, masked.max(axis=1), 0.0)
+    return SolveResult(X=ev["X"], value=ev["value"], violations=ev["violations"],
+                       wvalue=ev.get("wvalue"), best_head=best_head, best_value=best_value,
+                       steps=int(steps), stop_step=stop_step, seconds=seconds)

@@ -568,3 +568,53 @@ def test_train_step_teacher_forced_late_steps(t_at):
     assert_close_scalar(T_gpu[0, cfg.S], to["entropy"], to["entropy"] + 1e-9, what="S(P)")
     assert int(sol.step_counter.item()) == t + 1
     sol.close()
+
+
+@pytest.mark.parametrize("problem", ["mis", "maxcut"])
+def test_solve_trains_rounds_and_scores_every_head(problem):
+    """solve(): T replayed steps from seeded parameters, then the trained logits rounded
+    and scored -- the same bits as driving CPRASolver by hand, scores equal to the
+    oracle's exact evaluation of the returned X, and the best feasible head chosen."""
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.solver import solve
+    g = random_regular_graph(400, 3, 21)
+    dg = api.DeviceGraph.from_csr(g)
+    S = 8
+    cfg = CPRAConfig(problem=problem, layer_kind="gcn", n_layers=2, hidden=16, S=S, T=300, lr=1e-2)
+    lam = np.linspace(0.5, 3, S).astype(np.float32) if problem == "mis" else None
+    say(f"solve {problem} N={g.n} S={S} T={cfg.T}")
+    r = solve(dg, cfg, lam=lam, seed=4)
+    ref = CPRASolver(dg, cfg, lam)
+    ref.load_params(init_params("gcn", g.n, 2, 16, S, seed=4))
+    ref.run(cfg.T)
+    ref.forward()
+    ev = ref.evaluate()
+    ref.close()
+    assert r.steps == cfg.T and r.stop_step is None
+    assert np.array_equal(r.X, ev["X"]) and np.array_equal(r.value, ev["value"])
+    e = oev.evaluate_one(r.X, g, problem)
+    if problem == "mis":
+        assert np.array_equal(r.value[0], e["size"])
+        assert np.array_equal(r.violations[0], e["violations"])
+    else:
+        assert np.array_equal(r.value[0], e["cut_edges"])
+        assert not r.violations.any()
+    feas = r.violations[0] == 0
+    assert feas.any()
+    assert r.best_head[0] >= 0 and feas[r.best_head[0]]
+    assert r.best_value[0] == r.value[0][feas].max()
+    say(f"  best head {r.best_head[0]}: {r.best_value[0]:.0f} in {r.seconds:.3f} s")
+
+
+def test_solve_with_early_stopping_reports_the_firing_step():
+    """solve(early_stopping=...): a tolerance that every step meets fires the rule
+    after `patience` stalled steps; the result names that step."""
+    api, CPRAConfig, CPRASolver = mods()
+    from paper_2402_02190_amd.solver import solve
+    g = random_regular_graph(200, 3, 22)
+    S = 4
+    cfg = CPRAConfig(problem="mis", layer_kind="gcn", n_layers=2, hidden=8, S=S, T=400)
+    r = solve(g, cfg, seed=1, early_stopping={"tol": 1e30, "patience": 7})
+    say(f"  stopped at step {r.stop_step} after {r.steps} replayed steps")
+    assert r.stop_step == 7
+    assert r.steps <= cfg.T
