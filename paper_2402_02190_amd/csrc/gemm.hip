@@ -90,7 +90,10 @@ const char* kCfgNames[kNumCfgs] = {"64x64x32_w2x2",   "64x64x32_w2x1", "64x64x32
                                    "128x64x16_w2x2_p2", "64x128x16_w2x2_p2",
                                    "128x128x16_w2x2_p2", "64x32x16_w1x1_p2",
                                    "32x64x16_w1x1_p2", "64x64x16_w1x1_p2",
-                                   "64x64x16_w2x1_p2", "128x64x16_w2x1_p2"};
+                                   "64x64x16_w2x1_p2", "128x64x16_w2x1_p2",
+                                   "64x64x16_w2x2_il", "128x128x16_w2x2_il",
+                                   "128x64x16_w2x2_il", "256x128x16_w2x2_il",
+                                   "64x128x16_w2x2_il"};
 
 struct Plan {
   int cfg, splits;

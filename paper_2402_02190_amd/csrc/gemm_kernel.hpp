@@ -24,10 +24,25 @@
 //         contraction runs over the graph's rows only.
 #pragma once
 
+#include <utility>
+
 #include "common.hpp"
 
 namespace cpra {
 namespace gemmk {
+
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>): a loop
+// whose index is a compile-time constant in every copy of the body, so arrays
+// it indexes stay in registers however large the body is (a #pragma unroll
+// may be declined past the unroller's size limit).
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -73,11 +88,22 @@ struct LaunchArgs {
   int row_counts[3];
 };
 
-// One operand tile [BK][R] in LDS, loaded by NT threads as float4 vectors.
-template <int R, int BK, int NT, bool KCONTIG>
+// One operand tile (R rows or columns of the output by BK steps of K) in LDS,
+// loaded by NT threads as float4 vectors.  Layout [BK][LD] (K-contiguous
+// operands transposed while stored, LD = R + 1; others LD = R + 4), or with
+// ROWK a K-contiguous tile kept [R][LDK] (LDK = BK + 4), stored in whole float4s.
+// The interleaved loop reads MFMA operands with k = h * BK/2 + kk for
+// half-wavefront h and MFMA kk (any order of a tile's k works when both operands
+// use it): in the [R][LDK] layout a lane's operands of a tile are BK/2
+// consecutive floats, read as float4s.
+template <int R, int BK, int NT, bool KCONTIG, bool ROWK = false>
 struct Tile {
+  static constexpr bool RK = KCONTIG && ROWK;
   static constexpr int PAD = KCONTIG ? 1 : 4;
-  static constexpr int LD = R + PAD;  // LDS row stride (floats)
+  static constexpr int LD = R + PAD;  // [BK][LD] layout: row stride (floats)
+  static constexpr int LDK = BK + 4;  // [R][LDK] layout: row stride (floats)
+  static constexpr int SIZE = RK ? R * LDK : BK * LD;  // floats of LDS
+  static constexpr int NREAD = RK ? BK / 8 : BK / 2;   // operand reads per row, interleaved loop
   static constexpr int NV = R * BK / 4 / NT;
   static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
   float4 reg[NV];
@@ -168,7 +194,11 @@ struct Tile {
       const int idx = tid + v * NT;
       const bool val = (ok >> v) & 1u;
       const float4 x = val ? reg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (KCONTIG) {
+      if constexpr (RK) {
+        const int r = idx / (BK / 4);
+        const int kq = (idx % (BK / 4)) * 4;
+        *reinterpret_cast<float4*>(Xs + r * LDK + kq) = x;
+      } else if constexpr (KCONTIG) {
         const int r = idx / (BK / 4);
         const int kq = (idx % (BK / 4)) * 4;
         Xs[(kq + 0) * LD + r] = x.x;
@@ -180,6 +210,73 @@ struct Tile {
         const int rq = (idx % (R / 4)) * 4;
         *reinterpret_cast<float4*>(Xs + k * LD + rq) = x;
       }
+    }
+  }
+
+  // Vector v of load_clamped / store_masked alone (the interleaved loop spreads
+  // them between MFMAs); load_one<0> starts a new `ok` mask.
+  template <int v>
+  __device__ inline void load_one(const float* __restrict__ X, int64_t ld, int mn0, int mn_lim, int k0,
+                                  int k_lim, int tid) {
+    const int idx = tid + v * NT;
+    bool val;
+    if constexpr (KCONTIG) {
+      const int r = idx / (BK / 4);
+      const int kq = (idx % (BK / 4)) * 4;
+      const int gm = min(mn0 + r, mn_lim - 1);
+      val = k0 + kq < k_lim;
+      const int gk = val ? k0 + kq : k_lim - 4;
+      reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gm * ld + gk);
+    } else {
+      const int k = idx / (R / 4);
+      const int rq = (idx % (R / 4)) * 4;
+      val = k0 + k < k_lim;
+      const int gk = val ? k0 + k : k_lim - 1;
+      const int gm = min(mn0 + rq, mn_lim - 4);
+      reg[v] = *reinterpret_cast<const float4*>(X + (int64_t)gk * ld + gm);
+    }
+    if constexpr (v == 0) ok = (unsigned)val;
+    else ok |= (unsigned)val << v;
+  }
+  template <int v>
+  __device__ inline void store_one(float* __restrict__ Xs, int tid) const {
+    const int idx = tid + v * NT;
+    // vectors past K become +0 by clearing their bits: no select, so no branch
+    // splits the MFMA slots around the store
+    const unsigned keep = 0u - ((ok >> v) & 1u);
+    const float4 x = make_float4(__uint_as_float(__float_as_uint(reg[v].x) & keep),
+                                 __uint_as_float(__float_as_uint(reg[v].y) & keep),
+                                 __uint_as_float(__float_as_uint(reg[v].z) & keep),
+                                 __uint_as_float(__float_as_uint(reg[v].w) & keep));
+    if constexpr (RK) {
+      const int r = idx / (BK / 4);
+      const int kq = (idx % (BK / 4)) * 4;
+      *reinterpret_cast<float4*>(Xs + r * LDK + kq) = x;
+    } else if constexpr (KCONTIG) {
+      const int r = idx / (BK / 4);
+      const int kq = (idx % (BK / 4)) * 4;
+      Xs[(kq + 0) * LD + r] = x.x;
+      Xs[(kq + 1) * LD + r] = x.y;
+      Xs[(kq + 2) * LD + r] = x.z;
+      Xs[(kq + 3) * LD + r] = x.w;
+    } else {
+      const int k = idx / (R / 4);
+      const int rq = (idx % (R / 4)) * 4;
+      *reinterpret_cast<float4*>(Xs + k * LD + rq) = x;
+    }
+  }
+  // Read q of the interleaved loop's operands of row or column mn for
+  // half-wavefront h: v[kk] for k = h * BK/2 + kk.
+  template <int q>
+  __device__ static inline void read_part(const float* Xs, int mn, int h, float (&v)[BK / 2]) {
+    if constexpr (RK) {
+      const float4 x = *reinterpret_cast<const float4*>(Xs + mn * LDK + h * (BK / 2) + 4 * q);
+      v[4 * q + 0] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    } else {
+      v[q] = Xs[(h * (BK / 2) + q) * LD + mn];
     }
   }
 
@@ -223,18 +320,29 @@ __device__ inline void epilogue_store(const ProbDev& P, float* C, int row, int c
 // B_T: B stored [N, K] (K contiguous); otherwise [K, N].
 // PF: prefetch distance in K tiles (1: the next tile is loaded while the
 // current one is multiplied; 2: two tiles ahead, in two register sets, so a
-// load has two K steps of MFMA work to land).
+// load has two K steps of MFMA work to land; 3: the interleaved loop, loads
+// three tiles ahead with the step's work spread between its MFMAs).
 // GM: group mode (0 none, 1 by rows, 2 by K).
+// Waves per SIMD the register allocation aims for: one where a wave holds
+// eight or more 32x32 accumulators (the whole register file is then one
+// wave's), else the compiler's default.
+template <int BM, int BN, int WM, int WN>
+constexpr int min_waves_per_eu() {
+  return (BM / (32 * WM)) * (BN / (32 * WN)) >= 8 ? 1 : 0;
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF, int GM>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
+__global__ __launch_bounds__(64 * WM * WN)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<BM, BN, WM, WN>(), min_waves_per_eu<BM, BN, WM, WN>())))
+void k_gemm(LaunchArgs args) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / (32 * WM);  // 32x32 accumulators per wave along M
   constexpr int TN = BN / (32 * WN);
   static_assert(TM >= 1 && TN >= 1 && TM * 32 * WM == BM && TN * 32 * WN == BN, "bad tiling");
-  using TA = Tile<BM, BK, NT, !A_T>;
-  using TB = Tile<BN, BK, NT, B_T>;
-  __shared__ __attribute__((aligned(16))) float As[2][BK * TA::LD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK * TB::LD];
+  using TA = Tile<BM, BK, NT, !A_T, PF == 3>;
+  using TB = Tile<BN, BK, NT, B_T, PF == 3>;
+  __shared__ __attribute__((aligned(16))) float As[2][TA::SIZE];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TB::SIZE];
 
   // XCD-aware order: the hardware deals consecutive block ids round-robin to
   // the 8 XCDs, each with its own L2.
@@ -318,11 +426,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
+  // the operands of both K pieces, read from the arguments once
+  const float* const A0p = P.A[0];
+  const float* const A1p = P.A[1];
+  const float* const B0p = P.B[0] + b_off;
+  const float* const B1p = P.B[1] + b_off;
+  const int64_t lda0 = P.lda[0], lda1 = P.lda[1], ldb0 = P.ldb[0], ldb1 = P.ldb[1];
+  const int n_lim = P.N;
   auto load_into = [&](TA& ta, TB& tb, int kt) {
     const int pc = kt < nt0 ? 0 : 1;
     const int k0 = kb + (kt - (pc ? nt0 : 0)) * BK;
     const int kl = kb + (pc ? kn1 : kn0);
-    if constexpr (PF == 2) {
+    if constexpr (PF >= 2) {
       ta.load_clamped(P.A[pc], P.lda[pc], m0, m_lim, k0, kl, tid);
       tb.load_clamped(P.B[pc] + b_off, P.ldb[pc], n0, P.N, k0, kl, tid);
     } else {
@@ -389,7 +504,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
         __syncthreads();
       }
     }
-  } else {
+  } else if constexpr (PF == 2) {
     // Two register sets; the loop is unrolled by two so that every set is
     // named statically.  In the body for tile kt: LDS[cur] holds tile kt, set
     // `nxt` holds tile kt + 1 (stored to LDS[cur ^ 1] at the end), and set
@@ -427,6 +542,108 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
     }
   }
 
+  if constexpr (PF == 3) {
+    // Interleaved two-deep loop.  Two load register sets and two sets of MFMA
+    // operands; at the start of step kt (parity p): operand set p holds tile kt,
+    // LDS buffer p ^ 1 holds tile kt + 1, load set `nxt` holds tile kt + 2 (in
+    // flight), load set `fre` is free.  The step's MFMAs on set p are issued in
+    // slots; after each slot comes a fixed share of the step's other work, in
+    // this order over the step: the loads of tile kt + 3 into `fre`, the LDS
+    // stores of `nxt` into buffer p (whose operands every wave read in the
+    // previous step), the operand reads of tile kt + 1 from buffer p ^ 1.  A
+    // scheduling barrier after each slot keeps that order, so the work issues
+    // while the MFMAs occupy the matrix pipe.  Past the last tile the loads
+    // re-read it and the stores and reads move values that are never used.
+    // No bias gradient here (the launcher gives such problems another loop).
+    struct Frags {
+      float a[TM][BK / 2];
+      float b[TN][BK / 2];
+    };
+    constexpr int NL = TA::NV + TB::NV;           // loads, then as many stores
+    constexpr int NRA = TM * TA::NREAD, NRB = TN * TB::NREAD;
+    constexpr int NOPS = 2 * NL + NRA + NRB;
+    constexpr int NSLOT = (BK / 2) * TM * TN;
+    auto read_all = [&](int buf, Frags& f) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        static_for<TA::NREAD>([&](auto q) { TA::template read_part<decltype(q)::value>(As[buf], (wm * TM + i) * 32 + l32, half, f.a[i]); });
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        static_for<TB::NREAD>([&](auto q) { TB::template read_part<decltype(q)::value>(Bs[buf], (wn * TN + j) * 32 + l32, half, f.b[j]); });
+    };
+    auto mfma_all = [&](const Frags& f) {
+      static_for<NSLOT>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        constexpr int kk = sl / (TM * TN), i = (sl / TN) % TM, j = sl % TN;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i][kk], f.b[j][kk], acc[i][j], 0, 0, 0);
+      });
+    };
+    TA ta0, ta1;
+    TB tb0, tb1;
+    Frags f0, f1;
+    auto step = [&](int kt, int p, const Frags& cur, Frags& nxf, TA& fre_a, TB& fre_b, TA& nxt_a,
+                    TB& nxt_b) {
+      const int ktl = min(kt + 3, kt_end - 1);
+      const bool p1 = ktl >= nt0;
+      const int k0 = kb + (ktl - (p1 ? nt0 : 0)) * BK;
+      const int kl = kb + (p1 ? kn1 : kn0);
+      const float* const Ap = p1 ? A1p : A0p;
+      const float* const Bp = p1 ? B1p : B0p;
+      const int64_t la = p1 ? lda1 : lda0, lb = p1 ? ldb1 : ldb0;
+      float* const as_st = As[p];
+      float* const bs_st = Bs[p];
+      const float* const as_rd = As[p ^ 1];
+      const float* const bs_rd = Bs[p ^ 1];
+      static_for<NSLOT>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        constexpr int kk = sl / (TM * TN), i = (sl / TN) % TM, j = sl % TN;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.a[i][kk], cur.b[j][kk], acc[i][j], 0, 0, 0);
+        static_for<NOPS>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          if constexpr (o * NSLOT / NOPS == sl) {
+            if constexpr (o < TA::NV) {
+              fre_a.template load_one<o>(Ap, la, m0, m_lim, k0, kl, tid);
+            } else if constexpr (o < NL) {
+              fre_b.template load_one<o - TA::NV>(Bp, lb, n0, n_lim, k0, kl, tid);
+            } else if constexpr (o < NL + TA::NV) {
+              nxt_a.template store_one<o - NL>(as_st, tid);
+            } else if constexpr (o < 2 * NL) {
+              nxt_b.template store_one<o - NL - TA::NV>(bs_st, tid);
+            } else if constexpr (o < 2 * NL + NRA) {
+              constexpr int r = o - 2 * NL;
+              TA::template read_part<r % TA::NREAD>(as_rd, (wm * TM + r / TA::NREAD) * 32 + l32, half,
+                                                    nxf.a[r / TA::NREAD]);
+            } else {
+              constexpr int r = o - 2 * NL - NRA;
+              TB::template read_part<r % TB::NREAD>(bs_rd, (wn * TN + r / TB::NREAD) * 32 + l32, half,
+                                                    nxf.b[r / TB::NREAD]);
+            }
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      __syncthreads();
+    };
+    if (kt_begin < kt_end) {
+      load_into(ta0, tb0, kt_begin);
+      load_into(ta1, tb1, min(kt_begin + 1, kt_end - 1));
+      ta0.store_masked(As[0], tid);
+      tb0.store_masked(Bs[0], tid);
+      __syncthreads();
+      read_all(0, f0);
+      ta1.store_masked(As[1], tid);
+      tb1.store_masked(Bs[1], tid);
+      load_into(ta0, tb0, min(kt_begin + 2, kt_end - 1));
+      __syncthreads();
+      int kt = kt_begin;
+      for (; kt + 1 < kt_end; kt += 2) {
+        step(kt, 0, f0, f1, ta1, tb1, ta0, tb0);
+        step(kt + 1, 1, f1, f0, ta0, tb0, ta1, tb1);
+      }
+      if (kt < kt_end) mfma_all(f0);  // odd count: the last tile's operands are in set 0
+    }
+  }
+
   // Accumulator layout of the 32x32 MFMA: register r of lane l holds
   // D[8*(r/4) + 4*(l/32) + r%4][l%32].
   const bool partial = args.splits > 1;
@@ -434,12 +651,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
   float* part = partial
                     ? args.partial + P.part_off + ((int64_t)split * GE + grp) * P.M * P.n_eff
                     : nullptr;
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
+  static_for<TM>([&](auto i) {
+    static_for<TN>([&](auto j) {
       const int col = n0 + (wn * TN + j) * 32 + l32;
-      if (col >= P.N) continue;
+      if (col >= P.N) return;
       const float bv = (!partial && bias_g) ? bias_g[col] : 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -452,8 +667,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(LaunchArgs args) {
           epilogue_store(P, Cg, row, col, v + bv);
         }
       }
-    }
-  }
+    });
+  });
   if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
     float* red = As[0];
     if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
@@ -494,6 +709,13 @@ constexpr Cfg kCfgs[] = {
     {64, 64, 16, 1, 1},    // 17: 64 threads, 64x64 per wave
     {64, 64, 16, 2, 1},    // 18: 128 threads, 32x64 per wave
     {128, 64, 16, 2, 1},   // 19: 128 threads, 64x64 per wave
+    // interleaved two-deep loop (MFMA slots with the step's loads, stores and
+    // operand reads between them); not for products with a bias gradient
+    {64, 64, 16, 2, 2},    // 20
+    {128, 128, 16, 2, 2},  // 21
+    {128, 64, 16, 2, 2},   // 22
+    {256, 128, 16, 2, 2},  // 23: 128x64 per wave, one wave per SIMD
+    {64, 128, 16, 2, 2},   // 24
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -502,7 +724,7 @@ constexpr int bm_index(int bm) { return bm == 32 ? 0 : bm == 64 ? 1 : 2; }
 
 // ---- launching ---------------------------------------------------------------
 template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF, int GM>
-void launch_cfg(LaunchArgs& args, hipStream_t stream) {
+void launch_tiles(LaunchArgs& args, hipStream_t stream) {
   int max_tiles = 0;
   for (int i = 0; i < args.n_prob; ++i) {
     ProbDev& d = args.p[i];
@@ -522,6 +744,14 @@ void launch_cfg(LaunchArgs& args, hipStream_t stream) {
   }
   hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>), grid, dim3(64 * WM * WN), 0,
                      stream, args);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool A_T, bool B_T, int PF, int GM>
+void launch_cfg(LaunchArgs& args, hipStream_t stream) {
+  if constexpr (GM == 1 && BM > 128)  // row-tile maps exist for heights up to 128
+    launch_tiles<128, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream);
+  else
+    launch_tiles<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream);
 }
 
 // Whether the branch-free loads of the two-deep-prefetch configurations may
@@ -544,12 +774,25 @@ inline bool pf2_ok(const LaunchArgs& args, bool a_t, bool b_t) {
 }
 
 // one-deep configuration standing in for a two-deep one (similar tile shape)
-constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3};
+constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3,
+                            6, 7, 3, 7, 4};
+// two-deep configuration standing in for an interleaved one where a problem wants
+// a bias gradient
+constexpr int kIlTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
+                           10, 14, 12, 14, 13};
+static_assert(sizeof(kIlTwin) / sizeof(kIlTwin[0]) == kNumCfgs, "one twin per configuration");
+
+inline bool wants_bias_grad(const LaunchArgs& args) {
+  for (int i = 0; i < args.n_prob; ++i)
+    if (args.p[i].bias_grad) return true;
+  return false;
+}
 static_assert(sizeof(kPf1Twin) / sizeof(kPf1Twin[0]) == kNumCfgs, "one twin per configuration");
 
 template <bool A_T, bool B_T, int GM>
 void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
   if (cfg >= 0 && cfg < kNumCfgs && !pf2_ok(args, A_T, B_T)) cfg = kPf1Twin[cfg];
+  if (cfg >= 0 && cfg < kNumCfgs && wants_bias_grad(args)) cfg = kIlTwin[cfg];
   switch (cfg) {
 #define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
   case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream); break;
@@ -573,6 +816,11 @@ void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
     CPRA_GEMM_CFG(17, 64, 64, 16, 1, 1, 2)
     CPRA_GEMM_CFG(18, 64, 64, 16, 2, 1, 2)
     CPRA_GEMM_CFG(19, 128, 64, 16, 2, 1, 2)
+    CPRA_GEMM_CFG(20, 64, 64, 16, 2, 2, 3)
+    CPRA_GEMM_CFG(21, 128, 128, 16, 2, 2, 3)
+    CPRA_GEMM_CFG(22, 128, 64, 16, 2, 2, 3)
+    CPRA_GEMM_CFG(23, 256, 128, 16, 2, 2, 3)
+    CPRA_GEMM_CFG(24, 64, 128, 16, 2, 2, 3)
 #undef CPRA_GEMM_CFG
     default: break;
   }
