@@ -52,14 +52,16 @@ def source_hash(family: str) -> str:
 
 def kernel_pattern(family: str) -> re.Pattern:
     """Regex on rocprofv3's demangled kernel name for a profiler family."""
-    # gemm_<layout>[_byrow|_byk]_<BM>x<BN>x<BK>_w<WM>x<WN>[_p2] -> k_gemm<BM, BN, BK, WM, WN,
-    # A_T, B_T, PF, GM> (PF: prefetch distance, GM: group mode 0 / 1 by rows / 2 by K)
-    m = re.fullmatch(r"gemm_([nt])([nt])(_byrow|_byk)?_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)(_p2)?", family)
+    # gemm_<layout>[_byrow|_byk]_<BM>x<BN>x<BK>_w<WM>x<WN>[_p2|_il] -> k_gemm<BM, BN, BK, WM, WN,
+    # A_T, B_T, PF, GM> (PF: 1 one-deep, 2 two-deep (_p2), 3 interleaved (_il); GM: group
+    # mode 0 / 1 by rows / 2 by K)
+    m = re.fullmatch(r"gemm_([nt])([nt])(_byrow|_byk)?_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)(_p2|_il)?", family)
     if m:
-        at, bt, grp, bm, bn, bk, wm, wn, p2 = m.groups()
+        at, bt, grp, bm, bn, bk, wm, wn, loop = m.groups()
         gm = {None: 0, "_byrow": 1, "_byk": 2}[grp]
+        pf = {None: 1, "_p2": 2, "_il": 3}[loop]
         args = f"{bm}, {bn}, {bk}, {wm}, {wn}, {'true' if at == 't' else 'false'}, " \
-               f"{'true' if bt == 't' else 'false'}, {2 if p2 else 1}, {gm}"
+               f"{'true' if bt == 't' else 'false'}, {pf}, {gm}"
         return re.compile(re.escape(f"k_gemm<{args}>"))
     if family == "gemm_splitk_reduce":
         return re.compile(r"k_gemm_splitk_reduce")

@@ -21,6 +21,10 @@ def test_kernel_pattern_maps_profiler_families_to_trace_names():
         "void cpra::gemmk::k_gemm<64, 64, 32, 2, 2, true, false, 2, 2>(x)")
     assert not TR.kernel_pattern("gemm_tn_64x64x32_w2x2_p2").search(
         "void cpra::gemmk::k_gemm<64, 64, 32, 2, 2, true, false, 2, 2>(x)")
+    assert TR.kernel_pattern("gemm_nn_64x64x16_w2x2_il").search(
+        "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 3, 0>(x)")
+    assert not TR.kernel_pattern("gemm_nn_64x64x16_w2x2_il").search(
+        "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 2, 0>(x)")
     assert TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, false>(a)")
     assert not TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, true>(a)")
     assert TR.kernel_pattern("loss_fwd_bwd").search("cpra::k_loss<2>(args)")
