@@ -91,18 +91,25 @@ struct LaunchArgs {
 // One operand tile (R rows or columns of the output by BK steps of K) in LDS,
 // loaded by NT threads as float4 vectors.  Layout [BK][LD] (K-contiguous
 // operands transposed while stored, LD = R + 1; others LD = R + 4), or with
-// ROWK a K-contiguous tile kept [R][LDK] (LDK = BK + 4), stored in whole float4s.
+// ROWK a K-contiguous tile kept [R][BK], stored in whole float4s.  In that
+// layout the 16-byte chunks of row r are permuted, chunk c at c ^ swz(r) with
+// swz(r) = (r / (64/BK)) mod (BK/4): the rows that share a 256-byte bank line
+// keep their chunks in place, so a store's 16 lanes fill the 64 banks once, and
+// a read of one chunk by 16 consecutive rows finds it at 16 different banks.
 // The interleaved loop reads MFMA operands with k = h * BK/2 + kk for
 // half-wavefront h and MFMA kk (any order of a tile's k works when both operands
-// use it): in the [R][LDK] layout a lane's operands of a tile are BK/2
+// use it): in the [R][BK] layout a lane's operands of a tile are BK/2
 // consecutive floats, read as float4s.
 template <int R, int BK, int NT, bool KCONTIG, bool ROWK = false>
 struct Tile {
   static constexpr bool RK = KCONTIG && ROWK;
   static constexpr int PAD = KCONTIG ? 1 : 4;
   static constexpr int LD = R + PAD;  // [BK][LD] layout: row stride (floats)
-  static constexpr int LDK = BK + 4;  // [R][LDK] layout: row stride (floats)
+  static constexpr int LDK = BK;  // [R][BK] layout: row stride (floats)
   static constexpr int SIZE = RK ? R * LDK : BK * LD;  // floats of LDS
+  static_assert(!RK || (BK >= 16 && 64 % BK == 0 && BK % 8 == 0), "[row][k] layout: BK 16 or 32");
+  // physical 16-byte chunk of logical chunk c in row r of the [R][BK] layout
+  __device__ static inline int chunk_at(int r, int c) { return c ^ ((r / (64 / BK)) % (BK / 4)); }
   static constexpr int NREAD = RK ? BK / 8 : BK / 2;   // operand reads per row, interleaved loop
   static constexpr int NV = R * BK / 4 / NT;
   static_assert(NV >= 1 && R * BK / 4 % NT == 0, "tile does not divide among the threads");
@@ -196,8 +203,8 @@ struct Tile {
       const float4 x = val ? reg[v] : make_float4(0.f, 0.f, 0.f, 0.f);
       if constexpr (RK) {
         const int r = idx / (BK / 4);
-        const int kq = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<float4*>(Xs + r * LDK + kq) = x;
+        const int c = idx % (BK / 4);
+        *reinterpret_cast<float4*>(Xs + r * LDK + 4 * chunk_at(r, c)) = x;
       } else if constexpr (KCONTIG) {
         const int r = idx / (BK / 4);
         const int kq = (idx % (BK / 4)) * 4;
@@ -250,8 +257,8 @@ struct Tile {
                                  __uint_as_float(__float_as_uint(reg[v].w) & keep));
     if constexpr (RK) {
       const int r = idx / (BK / 4);
-      const int kq = (idx % (BK / 4)) * 4;
-      *reinterpret_cast<float4*>(Xs + r * LDK + kq) = x;
+      const int c = idx % (BK / 4);
+      *reinterpret_cast<float4*>(Xs + r * LDK + 4 * chunk_at(r, c)) = x;
     } else if constexpr (KCONTIG) {
       const int r = idx / (BK / 4);
       const int kq = (idx % (BK / 4)) * 4;
@@ -270,7 +277,8 @@ struct Tile {
   template <int q>
   __device__ static inline void read_part(const float* Xs, int mn, int h, float (&v)[BK / 2]) {
     if constexpr (RK) {
-      const float4 x = *reinterpret_cast<const float4*>(Xs + mn * LDK + h * (BK / 2) + 4 * q);
+      const float4 x =
+          *reinterpret_cast<const float4*>(Xs + mn * LDK + 4 * chunk_at(mn, h * (BK / 8) + q));
       v[4 * q + 0] = x.x;
       v[4 * q + 1] = x.y;
       v[4 * q + 2] = x.z;
@@ -716,6 +724,8 @@ constexpr Cfg kCfgs[] = {
     {128, 64, 16, 2, 2},   // 22
     {256, 128, 16, 2, 2},  // 23: 128x64 per wave, one wave per SIMD
     {64, 128, 16, 2, 2},   // 24
+    {64, 64, 32, 2, 2},    // 25
+    {64, 128, 32, 2, 2},   // 26
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -775,11 +785,11 @@ inline bool pf2_ok(const LaunchArgs& args, bool a_t, bool b_t) {
 
 // one-deep configuration standing in for a two-deep one (similar tile shape)
 constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3,
-                            6, 7, 3, 7, 4};
+                            6, 7, 3, 7, 4, 0, 4};
 // two-deep configuration standing in for an interleaved one where a problem wants
 // a bias gradient
 constexpr int kIlTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
-                           10, 14, 12, 14, 13};
+                           10, 14, 12, 14, 13, 11, 13};
 static_assert(sizeof(kIlTwin) / sizeof(kIlTwin[0]) == kNumCfgs, "one twin per configuration");
 
 inline bool wants_bias_grad(const LaunchArgs& args) {
@@ -821,6 +831,8 @@ void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
     CPRA_GEMM_CFG(22, 128, 64, 16, 2, 2, 3)
     CPRA_GEMM_CFG(23, 256, 128, 16, 2, 2, 3)
     CPRA_GEMM_CFG(24, 64, 128, 16, 2, 2, 3)
+    CPRA_GEMM_CFG(25, 64, 64, 32, 2, 2, 3)
+    CPRA_GEMM_CFG(26, 64, 128, 32, 2, 2, 3)
 #undef CPRA_GEMM_CFG
     default: break;
   }
