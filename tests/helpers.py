@@ -116,3 +116,8 @@ def assert_update_close(after, before, ref_after, tol=TOL, what=""):
     say(f"  {what}: update rel_err (beyond one FP32 ulp)={e:.3e}")
     assert e <= tol, f"{what}: update error {e:.3e} > {tol}"
     return e
+
+
+# tile configurations the library's GEMM tuner chooses from (forced one by one in the
+# GEMM tests)
+N_GEMM_CFGS = 27

@@ -12,8 +12,8 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from helpers import (assert_close_array, assert_close_scalar, assert_update_close, need_gpu, rel_err,
-                     say, to_dev)
+from helpers import (N_GEMM_CFGS, assert_close_array, assert_close_scalar, assert_update_close, need_gpu,
+                     rel_err, say, to_dev)
 from oracle import evaluate as oev
 from oracle import gnn as ognn
 from oracle import objective as oobj
@@ -409,7 +409,6 @@ def test_round_eval_tiny_and_subnormal_logits():
     assert np.array_equal(vio.cpu().numpy(), e["violations"])
 
 
-N_GEMM_CFGS = 27  # tile configurations the library's tuner chooses from
 
 
 @pytest.mark.parametrize("cfg", range(N_GEMM_CFGS))

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import assert_close_array, assert_close_scalar, assert_update_close, check_relu_decisions, \
-    need_gpu, say, to_dev
+from helpers import N_GEMM_CFGS, assert_close_array, assert_close_scalar, assert_update_close, \
+    check_relu_decisions, need_gpu, say, to_dev
 from oracle import gnn as ognn
 from oracle import train as otrain
 from workloads import CSRGraph, disjoint_union, erdos_renyi_graph, init_params_per_graph, \
@@ -15,7 +15,6 @@ from workloads import CSRGraph, disjoint_union, erdos_renyi_graph, init_params_p
 
 pytestmark = pytest.mark.gpu
 
-N_GEMM_CFGS = 20
 
 
 @pytest.fixture(autouse=True)
