@@ -5,13 +5,20 @@
 //
 // A block computes a BM x BN tile with WM x WN wavefronts, each owning
 // TM x TN = (BM/32/WM) x (BN/32/WN) accumulators of 32 x 32.  K advances in
-// BK-deep steps staged through LDS in the [k][mn] layout (double buffered,
-// one barrier per step): the next step's global loads are issued before the
-// current step's MFMAs, all MFMA operands of a step are read from LDS into
-// registers before the first MFMA of the step, and K-contiguous operands are
-// transposed while being written to LDS so every operand read is 32
-// consecutive floats per half-wavefront.  Interior tiles take unguarded
-// float4 loads (a uniform branch); edge tiles fall back to guarded loads.
+// BK-deep steps staged through LDS (double buffered, one barrier per step),
+// in one of three loops (PF):
+//  * one-deep (1): the next step's global loads are issued before the current
+//    step's MFMAs; interior tiles take unguarded float4 loads (a uniform
+//    branch), edge tiles guarded ones;
+//  * two-deep (2): loads two steps ahead in two register sets, branch-free at
+//    clamped addresses;
+//  * interleaved (3): loads three steps ahead, the next tile's MFMA operands
+//    read into a second register set during the current MFMAs, and every
+//    MFMA of a step followed by a fixed share of the step's other work.
+// In the first two, tiles are [k][mn] in LDS (K-contiguous operands transposed
+// while stored, so an operand read is 32 consecutive floats per
+// half-wavefront); the interleaved loop keeps K-contiguous tiles [row][k]
+// (see Tile).
 //
 // Group modes (GM) for batches with one weight set per graph, graph g owning
 // rows gptr[g] .. gptr[g+1]-1 of the batch:
