@@ -94,7 +94,9 @@ const char* kCfgNames[kNumCfgs] = {"64x64x32_w2x2",   "64x64x32_w2x1", "64x64x32
                                    "64x64x16_w2x2_il", "128x128x16_w2x2_il",
                                    "128x64x16_w2x2_il", "256x128x16_w2x2_il",
                                    "64x128x16_w2x2_il", "64x64x32_w2x2_il",
-                                   "64x128x32_w2x2_il"};
+                                   "64x128x32_w2x2_il", "64x64x16_w2x2_ring",
+                                   "64x128x16_w2x2_ring", "128x64x16_w2x2_ring",
+                                   "64x64x32_w2x2_ring", "128x128x16_w2x2_ring"};
 
 struct Plan {
   int cfg, splits;
@@ -285,11 +287,8 @@ cpra_status run_plan(bool a_t, bool b_t, const GemmProblem* probs, int n, const 
                      hipStream_t stream) {
   LaunchArgs args;
   fill_args(probs, n, pl.splits, ws, &args);
-  // the configuration that runs (and names the profiler family): the one-deep twin
-  // where the branch-free loads may not run, the two-deep twin where the
-  // interleaved loop would need a bias gradient
-  int cfg = pf2_ok(args, a_t, b_t) ? pl.cfg : kPf1Twin[pl.cfg];
-  if (wants_bias_grad(args)) cfg = kIlTwin[cfg];
+  // the configuration that runs (and names the profiler family)
+  const int cfg = resolve_cfg(args, a_t, b_t, pl.cfg);
   double flops = 0, red_bytes = 0;
   for (int i = 0; i < n; ++i) {
     const double mn = (double)args.p[i].M * args.p[i].N;

@@ -5,8 +5,8 @@
 //
 // A block computes a BM x BN tile with WM x WN wavefronts, each owning
 // TM x TN = (BM/32/WM) x (BN/32/WN) accumulators of 32 x 32.  K advances in
-// BK-deep steps staged through LDS (double buffered, one barrier per step),
-// in one of three loops (PF):
+// BK-deep steps staged through LDS (one barrier per step), in one of four
+// loops (PF):
 //  * one-deep (1): the next step's global loads are issued before the current
 //    step's MFMAs; interior tiles take unguarded float4 loads (a uniform
 //    branch), edge tiles guarded ones;
@@ -14,11 +14,13 @@
 //    clamped addresses;
 //  * interleaved (3): loads three steps ahead, the next tile's MFMA operands
 //    read into a second register set during the current MFMAs, and every
-//    MFMA of a step followed by a fixed share of the step's other work.
+//    MFMA of a step followed by a fixed share of the step's other work;
+//  * LDS ring (4): buffer loads write the tiles straight into a ring of four
+//    LDS stages (no registers, no LDS store instructions), three steps ahead,
+//    with the interleaved loop's operand reads between the MFMAs (see DmaTile).
 // In the first two, tiles are [k][mn] in LDS (K-contiguous operands transposed
 // while stored, so an operand read is 32 consecutive floats per
-// half-wavefront); the interleaved loop keeps K-contiguous tiles [row][k]
-// (see Tile).
+// half-wavefront); the last two keep K-contiguous tiles [row][k] (see Tile).
 //
 // Group modes (GM) for batches with one weight set per graph, graph g owning
 // rows gptr[g] .. gptr[g+1]-1 of the batch:
@@ -315,6 +317,92 @@ struct Tile {
   }
 };
 
+// One operand tile of the LDS-ring loop: R rows or columns of the output by BK
+// steps of K, R * BK floats per stage with no padding.  A buffer load with the
+// LDS flag writes the 16 bytes of lane l of a wavefront to LDS at the
+// instruction's base + 16 l, so a stage is filled in 16-byte slots, slot
+// v * NT + tid by vector v of thread tid, and the layout is chosen through the
+// global vector each thread fetches for its slot:
+//  * K-contiguous operands: [R][BK] with the chunk permutation of Tile's
+//    [row][k] layout (slot (r, c) holds logical chunk chunk_at(r, c), the
+//    permutation being its own inverse), read as float4s like Tile::read_part;
+//  * others: [BK][R] with the column index of the rows in the second half of
+//    the tile (k >= BK/2) XOR-ed with 32, so that the two half-wavefronts,
+//    which read k and k + BK/2 at the same 32 columns, meet different banks.
+// A vector outside the matrix (rows or columns past the edge, k past the
+// piece's end) is given a byte offset past the buffer's range, and the
+// hardware writes zeros for it; valid offsets are below 2^31 bytes (the
+// launcher checks the operands' extents).
+template <int R, int BK, int NT, bool KCONTIG>
+struct DmaTile {
+  static constexpr int SIZE = R * BK;  // floats per stage
+  static constexpr int NV = SIZE / 4 / NT;
+  static constexpr int NREAD = KCONTIG ? BK / 8 : BK / 2;
+  static constexpr unsigned kOut = 0x80000000u;  // offset past the range: reads as zero
+  static_assert(NV >= 1 && (SIZE / 4) % NT == 0, "tile does not divide among the threads");
+  static_assert(KCONTIG || (R >= 64 && R % 64 == 0), "[k][mn] stage: 64 or more columns");
+  using RowK = Tile<R, BK, NT, true, true>;
+  unsigned off[2][NV];  // per K piece: float offset of vector v without the k0 term
+  unsigned kq[NV];      // k of vector v within the tile
+  unsigned mn_ok;       // bit v: the vector's row or columns lie inside the matrix
+
+  __device__ inline void setup(int64_t ld0, int64_t ld1, int mn0, int mn_lim, int tid) {
+    mn_ok = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int s = v * NT + tid;
+      if constexpr (KCONTIG) {
+        const int r = s / (BK / 4);
+        const int c = RowK::chunk_at(r, s % (BK / 4));
+        const unsigned row = (unsigned)(mn0 + r);
+        off[0][v] = row * (unsigned)ld0 + 4u * c;
+        off[1][v] = row * (unsigned)ld1 + 4u * c;
+        kq[v] = 4u * c;
+        mn_ok |= (unsigned)(mn0 + r < mn_lim) << v;
+      } else {
+        const int k = s / (R / 4);
+        const int c = (s % (R / 4)) ^ (((k / (BK / 2)) & 1) * 8);
+        const unsigned col = (unsigned)(mn0 + 4 * c);
+        off[0][v] = (unsigned)k * (unsigned)ld0 + col;
+        off[1][v] = (unsigned)k * (unsigned)ld1 + col;
+        kq[v] = (unsigned)k;
+        mn_ok |= (unsigned)(mn0 + 4 * c < mn_lim) << v;
+      }
+    }
+  }
+  // Byte offset of vector v for the tile starting at k0 of piece pc (k_lim: the
+  // piece's end; ld: its leading dimension).
+  template <int v>
+  __device__ inline unsigned voffset(int pc, int k0, int k_lim, int64_t ld) const {
+    const bool ok = ((mn_ok >> v) & 1u) && (k0 + (int)kq[v] < k_lim);
+    const unsigned o = KCONTIG ? off[pc][v] + (unsigned)k0 : off[pc][v] + (unsigned)k0 * (unsigned)ld;
+    return ok ? 4u * o : kOut;
+  }
+  // Read q of the operands of row or column mn for half-wavefront h:
+  // v[kk] for k = h * BK/2 + kk.
+  template <int q>
+  __device__ static inline void read_part(const float* Xs, int mn, int h, float (&v)[BK / 2]) {
+    if constexpr (KCONTIG) {
+      RowK::template read_part<q>(Xs, mn, h, v);
+    } else {
+      v[q] = Xs[(h * (BK / 2) + q) * R + (mn ^ (32 * h))];
+    }
+  }
+};
+
+// One 16-byte buffer load per lane of base[voff] (voff in bytes; past 2^31 - 1:
+// zeros) into LDS at lds + 16 * lane (lds the same for the whole wavefront).
+// The size check of the builtin knows gfx950 only in the device pass.
+__device__ inline void load_lds16(const float* base, float* lds, unsigned voff) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+#endif
+}
+
+// s_waitcnt operand: vector-memory count at most `vm`, LDS count zero, export
+// count unchecked (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | (7 << 4) | ((vm >> 4) << 14); }
 
 // C[row, col] = mask(relu(v + add + beta C)) and optionally sigmoid(C) into sig_out.
 __device__ inline void epilogue_store(const ProbDev& P, float* C, int row, int col, float v) {
@@ -336,7 +424,8 @@ __device__ inline void epilogue_store(const ProbDev& P, float* C, int row, int c
 // PF: prefetch distance in K tiles (1: the next tile is loaded while the
 // current one is multiplied; 2: two tiles ahead, in two register sets, so a
 // load has two K steps of MFMA work to land; 3: the interleaved loop, loads
-// three tiles ahead with the step's work spread between its MFMAs).
+// three tiles ahead with the step's work spread between its MFMAs; 4: the
+// LDS ring, tiles written to LDS by the loads themselves, three tiles ahead).
 // GM: group mode (0 none, 1 by rows, 2 by K).
 // Waves per SIMD the register allocation aims for: one where a wave holds
 // eight or more 32x32 accumulators (the whole register file is then one
@@ -659,6 +748,151 @@ void k_gemm(LaunchArgs args) {
     }
   }
 
+  if constexpr (PF == 4) {
+    // LDS ring of D stages, tile kt in stage (kt - kt_begin) mod D.  At the start
+    // of step kt: operand set `cur` holds tile kt (read from its stage in the
+    // previous step) and the loads of tiles kt + 1 .. kt + D - 1 are issued.  The
+    // step waits for this wave's loads of tile kt + 1 and its own LDS reads, then
+    // the block barrier: tile kt + 1 is in LDS and no wave still reads the stage
+    // of tile kt, which receives tile kt + D.  The MFMAs of tile kt then run in
+    // slots, the loads of tile kt + D and the reads of tile kt + 1's operands
+    // placed between them.  Every stage is its own LDS array and the loop is
+    // unrolled by D, so the compiler tells the stages apart and never waits for
+    // loads of a later tile before an operand read.  The barrier is a plain
+    // s_barrier: a workgroup fence would wait for every load in flight.
+    // Past the last tile the loads re-read it into stages never read again.
+    // No bias gradient here (the launcher gives such problems another loop).
+    using DA = DmaTile<BM, BK, NT, !A_T>;
+    using DB = DmaTile<BN, BK, NT, B_T>;
+    constexpr int D = 4;
+    __shared__ __attribute__((aligned(16))) float Sa0[DA::SIZE], Sa1[DA::SIZE], Sa2[DA::SIZE], Sa3[DA::SIZE];
+    __shared__ __attribute__((aligned(16))) float Sb0[DB::SIZE], Sb1[DB::SIZE], Sb2[DB::SIZE], Sb3[DB::SIZE];
+    constexpr int NL = DA::NV + DB::NV;  // loads per thread and tile
+    static_assert((D - 1) * NL <= 63, "vmcnt range");
+    auto stage_a = [&](auto st) -> float* {
+      constexpr int x = decltype(st)::value;
+      if constexpr (x == 0) return Sa0;
+      else if constexpr (x == 1) return Sa1;
+      else if constexpr (x == 2) return Sa2;
+      else return Sa3;
+    };
+    auto stage_b = [&](auto st) -> float* {
+      constexpr int x = decltype(st)::value;
+      if constexpr (x == 0) return Sb0;
+      else if constexpr (x == 1) return Sb1;
+      else if constexpr (x == 2) return Sb2;
+      else return Sb3;
+    };
+    struct Frags {
+      float a[TM][BK / 2];
+      float b[TN][BK / 2];
+    };
+    constexpr int NRA = TM * DA::NREAD, NRB = TN * DB::NREAD;
+    constexpr int NOPS = NL + NRA + NRB;
+    constexpr int NSLOT = (BK / 2) * TM * TN;
+    DA da;
+    DB db;
+    da.setup(lda0, lda1, m0, m_lim, tid);
+    db.setup(ldb0, ldb1, n0, n_lim, tid);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // operand o of the loads of tile kt into stage st (o < NL)
+    struct TileRef {
+      int pc, k0, kl;
+    };
+    auto tile_ref = [&](int kt) {
+      TileRef t;
+      t.pc = kt < nt0 ? 0 : 1;
+      t.k0 = kb + (kt - (t.pc ? nt0 : 0)) * BK;
+      t.kl = kb + (t.pc ? kn1 : kn0);
+      return t;
+    };
+    auto load_one = [&](auto oc, auto st, const TileRef& t) {
+      constexpr int o = decltype(oc)::value;
+      if constexpr (o < DA::NV) {
+        load_lds16(t.pc ? A1p : A0p, stage_a(st) + (o * NT + wv * 64) * 4,
+                   da.template voffset<o>(t.pc, t.k0, t.kl, t.pc ? lda1 : lda0));
+      } else {
+        constexpr int v = o - DA::NV;
+        load_lds16(t.pc ? B1p : B0p, stage_b(st) + (v * NT + wv * 64) * 4,
+                   db.template voffset<v>(t.pc, t.k0, t.kl, t.pc ? ldb1 : ldb0));
+      }
+    };
+    auto load_all = [&](auto st, int kt) {
+      const TileRef t = tile_ref(kt);
+      static_for<NL>([&](auto oc) { load_one(oc, st, t); });
+    };
+    auto read_all = [&](auto st, Frags& f) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        static_for<DA::NREAD>([&](auto q) {
+          DA::template read_part<decltype(q)::value>(stage_a(st), (wm * TM + i) * 32 + l32, half, f.a[i]);
+        });
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        static_for<DB::NREAD>([&](auto q) {
+          DB::template read_part<decltype(q)::value>(stage_b(st), (wn * TN + j) * 32 + l32, half, f.b[j]);
+        });
+    };
+    auto sync = [&](auto vm) {
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(decltype(vm)::value));
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    };
+    // step kt in phase ph = (kt - kt_begin) mod D
+    auto step = [&](auto phc, int kt, const Frags& cur, Frags& nxf) {
+      constexpr int ph = decltype(phc)::value;
+      using StNow = std::integral_constant<int, ph>;
+      using StNext = std::integral_constant<int, (ph + 1) % D>;
+      sync(std::integral_constant<int, (D - 2) * NL>{});
+      const TileRef t = tile_ref(min(kt + D, kt_end - 1));
+      static_for<NSLOT>([&](auto sc) {
+        constexpr int sl = decltype(sc)::value;
+        constexpr int kk = sl / (TM * TN), i = (sl / TN) % TM, j = sl % TN;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur.a[i][kk], cur.b[j][kk], acc[i][j], 0, 0, 0);
+        static_for<NOPS>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          if constexpr (o * NSLOT / NOPS == sl) {
+            if constexpr (o < NL) {
+              load_one(oc, StNow{}, t);
+            } else if constexpr (o < NL + NRA) {
+              constexpr int r = o - NL;
+              DA::template read_part<r % DA::NREAD>(stage_a(StNext{}), (wm * TM + r / DA::NREAD) * 32 + l32,
+                                                    half, nxf.a[r / DA::NREAD]);
+            } else {
+              constexpr int r = o - NL - NRA;
+              DB::template read_part<r % DB::NREAD>(stage_b(StNext{}), (wn * TN + r / DB::NREAD) * 32 + l32,
+                                                    half, nxf.b[r / DB::NREAD]);
+            }
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    };
+    if (kt_begin < kt_end) {
+      Frags f0, f1;
+      static_for<D>([&](auto st) { load_all(st, min(kt_begin + decltype(st)::value, kt_end - 1)); });
+      sync(std::integral_constant<int, (D - 1) * NL>{});
+      read_all(std::integral_constant<int, 0>{}, f0);
+      int kt = kt_begin;
+      for (; kt + D <= kt_end; kt += D) {
+        static_for<D>([&](auto ph) {
+          constexpr int x = decltype(ph)::value;
+          if constexpr (x % 2 == 0) step(ph, kt + x, f0, f1);
+          else step(ph, kt + x, f1, f0);
+        });
+      }
+      static_for<D - 1>([&](auto ph) {
+        constexpr int x = decltype(ph)::value;
+        if (kt + x < kt_end) {
+          if constexpr (x % 2 == 0) step(ph, kt + x, f0, f1);
+          else step(ph, kt + x, f1, f0);
+        }
+      });
+      // the loads past the last tile land before the block may leave its LDS
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+    }
+  }
+
   // Accumulator layout of the 32x32 MFMA: register r of lane l holds
   // D[8*(r/4) + 4*(l/32) + r%4][l%32].
   const bool partial = args.splits > 1;
@@ -684,15 +918,17 @@ void k_gemm(LaunchArgs args) {
       }
     });
   });
-  if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
-    float* red = As[0];
-    if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
-    __syncthreads();
-    if (tid < BM && m0 + tid < m_lim) {
-      float v = 0.f;
-      for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
-      if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
-      else bgrad_g[m0 + tid] = v;
+  if constexpr (PF != 4) {
+    if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
+      float* red = As[0];
+      if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
+      __syncthreads();
+      if (tid < BM && m0 + tid < m_lim) {
+        float v = 0.f;
+        for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
+        if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
+        else bgrad_g[m0 + tid] = v;
+      }
     }
   }
 }
@@ -733,6 +969,13 @@ constexpr Cfg kCfgs[] = {
     {64, 128, 16, 2, 2},   // 24
     {64, 64, 32, 2, 2},    // 25
     {64, 128, 32, 2, 2},   // 26
+    // LDS ring (tiles written to LDS by the loads, three steps ahead); not for
+    // products with a bias gradient
+    {64, 64, 16, 2, 2},    // 27
+    {64, 128, 16, 2, 2},   // 28
+    {128, 64, 16, 2, 2},   // 29
+    {64, 64, 32, 2, 2},    // 30
+    {128, 128, 16, 2, 2},  // 31
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -792,12 +1035,17 @@ inline bool pf2_ok(const LaunchArgs& args, bool a_t, bool b_t) {
 
 // one-deep configuration standing in for a two-deep one (similar tile shape)
 constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3,
-                            6, 7, 3, 7, 4, 0, 4};
-// two-deep configuration standing in for an interleaved one where a problem wants
-// a bias gradient
+                            6, 7, 3, 7, 4, 0, 4, 6, 4, 3, 0, 7};
+// two-deep configuration standing in for an interleaved or LDS-ring one where a
+// problem wants a bias gradient
 constexpr int kIlTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
-                           10, 14, 12, 14, 13, 11, 13};
+                           10, 14, 12, 14, 13, 11, 13, 10, 13, 12, 11, 14};
+// interleaved configuration standing in for an LDS-ring one whose operands
+// reach past the 2^31-byte offsets of its buffer loads
+constexpr int kRingTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
+                             20, 21, 22, 23, 24, 25, 26, 20, 24, 22, 25, 21};
 static_assert(sizeof(kIlTwin) / sizeof(kIlTwin[0]) == kNumCfgs, "one twin per configuration");
+static_assert(sizeof(kRingTwin) / sizeof(kRingTwin[0]) == kNumCfgs, "one twin per configuration");
 
 inline bool wants_bias_grad(const LaunchArgs& args) {
   for (int i = 0; i < args.n_prob; ++i)
@@ -806,10 +1054,38 @@ inline bool wants_bias_grad(const LaunchArgs& args) {
 }
 static_assert(sizeof(kPf1Twin) / sizeof(kPf1Twin[0]) == kNumCfgs, "one twin per configuration");
 
+// Whether every operand of the launch lies within 2^31 bytes of its base, as
+// the 32-bit byte offsets of the LDS-ring loop's buffer loads need.
+inline bool ring_ok(const LaunchArgs& args, bool a_t, bool b_t) {
+  const double lim = 2147483648.0 - 64.0;
+  for (int i = 0; i < args.n_prob; ++i) {
+    const ProbDev& d = args.p[i];
+    if (d.M <= 0) continue;
+    for (int pc = 0; pc < d.n_pieces; ++pc) {
+      const double ra = a_t ? d.K[pc] : d.M, ca = a_t ? d.M : d.K[pc];
+      const double rb = b_t ? d.N : d.K[pc], cb = b_t ? d.K[pc] : d.N;
+      if (4.0 * (ra * (double)d.lda[pc] + ca) >= lim) return false;
+      if (4.0 * (rb * (double)d.ldb[pc] + cb) >= lim) return false;
+    }
+  }
+  return true;
+}
+
+// The configuration that runs for a requested one: the one-deep twin where the
+// branch-free loads may not run, the two-deep twin where the interleaved or
+// ring loop would need a bias gradient, the interleaved twin where the ring's
+// offsets would not reach.
+inline int resolve_cfg(const LaunchArgs& args, bool a_t, bool b_t, int cfg) {
+  if (cfg < 0 || cfg >= kNumCfgs) return cfg;
+  if (!pf2_ok(args, a_t, b_t)) cfg = kPf1Twin[cfg];
+  if (wants_bias_grad(args)) cfg = kIlTwin[cfg];
+  if (!ring_ok(args, a_t, b_t)) cfg = kRingTwin[cfg];
+  return cfg;
+}
+
 template <bool A_T, bool B_T, int GM>
 void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
-  if (cfg >= 0 && cfg < kNumCfgs && !pf2_ok(args, A_T, B_T)) cfg = kPf1Twin[cfg];
-  if (cfg >= 0 && cfg < kNumCfgs && wants_bias_grad(args)) cfg = kIlTwin[cfg];
+  cfg = resolve_cfg(args, A_T, B_T, cfg);
   switch (cfg) {
 #define CPRA_GEMM_CFG(I, BM, BN, BK, WM, WN, PF) \
   case I: launch_cfg<BM, BN, BK, WM, WN, A_T, B_T, PF, GM>(args, stream); break;
@@ -840,6 +1116,11 @@ void launch_any(int cfg, LaunchArgs& args, hipStream_t stream) {
     CPRA_GEMM_CFG(24, 64, 128, 16, 2, 2, 3)
     CPRA_GEMM_CFG(25, 64, 64, 32, 2, 2, 3)
     CPRA_GEMM_CFG(26, 64, 128, 32, 2, 2, 3)
+    CPRA_GEMM_CFG(27, 64, 64, 16, 2, 2, 4)
+    CPRA_GEMM_CFG(28, 64, 128, 16, 2, 2, 4)
+    CPRA_GEMM_CFG(29, 128, 64, 16, 2, 2, 4)
+    CPRA_GEMM_CFG(30, 64, 64, 32, 2, 2, 4)
+    CPRA_GEMM_CFG(31, 128, 128, 16, 2, 2, 4)
 #undef CPRA_GEMM_CFG
     default: break;
   }

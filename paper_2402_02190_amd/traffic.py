@@ -52,14 +52,14 @@ def source_hash(family: str) -> str:
 
 def kernel_pattern(family: str) -> re.Pattern:
     """Regex on rocprofv3's demangled kernel name for a profiler family."""
-    # gemm_<layout>[_byrow|_byk]_<BM>x<BN>x<BK>_w<WM>x<WN>[_p2|_il] -> k_gemm<BM, BN, BK, WM, WN,
-    # A_T, B_T, PF, GM> (PF: 1 one-deep, 2 two-deep (_p2), 3 interleaved (_il); GM: group
-    # mode 0 / 1 by rows / 2 by K)
-    m = re.fullmatch(r"gemm_([nt])([nt])(_byrow|_byk)?_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)(_p2|_il)?", family)
+    # gemm_<layout>[_byrow|_byk]_<BM>x<BN>x<BK>_w<WM>x<WN>[_p2|_il|_ring] -> k_gemm<BM, BN, BK,
+    # WM, WN, A_T, B_T, PF, GM> (PF: 1 one-deep, 2 two-deep (_p2), 3 interleaved (_il), 4 LDS
+    # ring (_ring); GM: group mode 0 / 1 by rows / 2 by K)
+    m = re.fullmatch(r"gemm_([nt])([nt])(_byrow|_byk)?_(\d+)x(\d+)x(\d+)_w(\d+)x(\d+)(_p2|_il|_ring)?", family)
     if m:
         at, bt, grp, bm, bn, bk, wm, wn, loop = m.groups()
         gm = {None: 0, "_byrow": 1, "_byk": 2}[grp]
-        pf = {None: 1, "_p2": 2, "_il": 3}[loop]
+        pf = {None: 1, "_p2": 2, "_il": 3, "_ring": 4}[loop]
         args = f"{bm}, {bn}, {bk}, {wm}, {wn}, {'true' if at == 't' else 'false'}, " \
                f"{'true' if bt == 't' else 'false'}, {pf}, {gm}"
         return re.compile(re.escape(f"k_gemm<{args}>"))

@@ -120,4 +120,4 @@ def assert_update_close(after, before, ref_after, tol=TOL, what=""):
 
 # tile configurations the library's GEMM tuner chooses from (forced one by one in the
 # GEMM tests)
-N_GEMM_CFGS = 27
+N_GEMM_CFGS = 32

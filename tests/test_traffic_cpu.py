@@ -25,6 +25,8 @@ def test_kernel_pattern_maps_profiler_families_to_trace_names():
         "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 3, 0>(x)")
     assert not TR.kernel_pattern("gemm_nn_64x64x16_w2x2_il").search(
         "void cpra::gemmk::k_gemm<64, 64, 16, 2, 2, false, false, 2, 0>(x)")
+    assert TR.kernel_pattern("gemm_nt_64x128x16_w2x2_ring").search(
+        "void cpra::gemmk::k_gemm<64, 128, 16, 2, 2, false, true, 4, 0>(x)")
     assert TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, false>(a)")
     assert not TR.kernel_pattern("aggregate").search("k_aggregate<4, 1, true>(a)")
     assert TR.kernel_pattern("loss_fwd_bwd").search("cpra::k_loss<2>(args)")
