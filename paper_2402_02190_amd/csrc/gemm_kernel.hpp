@@ -330,17 +330,16 @@ struct Tile {
 //    the tile (k >= BK/2) XOR-ed with 32, so that the two half-wavefronts,
 //    which read k and k + BK/2 at the same 32 columns, meet different banks.
 // A vector outside the matrix (rows or columns past the edge, k past the
-// piece's end) is given a byte offset past the buffer's range, and the
-// hardware writes zeros for it; valid offsets are below 2^31 bytes (the
-// launcher checks the operands' extents).
+// piece's end) is given a byte offset past the buffer's range (2^31 - 1
+// bytes), and the hardware writes zeros for it; valid offsets are below 2^31
+// bytes (the launcher checks the operands' extents).
 template <int R, int BK, int NT, bool KCONTIG>
 struct DmaTile {
   static constexpr int SIZE = R * BK;  // floats per stage
   static constexpr int NV = SIZE / 4 / NT;
   static constexpr int NREAD = KCONTIG ? BK / 8 : BK / 2;
-  static constexpr unsigned kOut = 0x80000000u;  // offset past the range: reads as zero
   static_assert(NV >= 1 && (SIZE / 4) % NT == 0, "tile does not divide among the threads");
-  static_assert(KCONTIG || (R >= 64 && R % 64 == 0), "[k][mn] stage: 64 or more columns");
+  static_assert(KCONTIG || R % 64 == 0, "[k][mn] stage: a multiple of 64 columns");
   using RowK = Tile<R, BK, NT, true, true>;
   unsigned off[2][NV];  // per K piece: float offset of vector v without the k0 term
   unsigned kq[NV];      // k of vector v within the tile
@@ -371,12 +370,14 @@ struct DmaTile {
     }
   }
   // Byte offset of vector v for the tile starting at k0 of piece pc (k_lim: the
-  // piece's end; ld: its leading dimension).
+  // piece's end; ld: its leading dimension).  A vector outside the matrix gets
+  // bit 31 set, which puts it past the buffer's range whatever the rest holds
+  // (valid offsets stay below 2^31): no select, so no branch.
   template <int v>
   __device__ inline unsigned voffset(int pc, int k0, int k_lim, int64_t ld) const {
-    const bool ok = ((mn_ok >> v) & 1u) && (k0 + (int)kq[v] < k_lim);
+    const unsigned ok = ((mn_ok >> v) & 1u) & (unsigned)(k0 + (int)kq[v] < k_lim);
     const unsigned o = KCONTIG ? off[pc][v] + (unsigned)k0 : off[pc][v] + (unsigned)k0 * (unsigned)ld;
-    return ok ? 4u * o : kOut;
+    return (4u * o) | ((ok ^ 1u) << 31);
   }
   // Read q of the operands of row or column mn for half-wavefront h:
   // v[kk] for k = h * BK/2 + kk.
