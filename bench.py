@@ -65,6 +65,12 @@ def build_workload(name: str, per_graph: bool = False):
 def make_solver(pr, g, params, per_graph: bool = False, edge_weight=None):
     from paper_2402_02190_amd import api
     from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
+    # capture order of the backward's forks, chosen per workload by step time (the
+    # library reads the switch whenever it records a step)
+    if pr.side_first:
+        os.environ["CPRA_SIDE_FIRST"] = "1"
+    else:
+        os.environ.pop("CPRA_SIDE_FIRST", None)
     dg = api.DeviceGraph.from_csr(g)
     cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
                      hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu,
@@ -340,6 +346,7 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
                    "problem": pr.problem, "recompute": bool(pr.recompute),
+                   "backward_fork_order": "side work first" if pr.side_first else "input gradient first",
                    "hip_graph_replay": True, "per_graph_weights": bool(per_graph),
                    "autotuned_gemm": not args.no_autotune,
                    "ms_per_step_events": ms_event,

@@ -274,7 +274,11 @@ cpra_status check_adam_cfg(const cpra_adam_cfg* cfg);
 
 // Side stream of the current device (see streams.hip).  fork_to makes the side
 // stream wait for everything enqueued so far on `main`; join_from makes `main`
-// wait for everything enqueued so far on the side stream.
+// wait for everything enqueued so far on the side stream.  fork_mark +
+// fork_wait is fork_to in two halves: the side stream waits for what `main` had
+// enqueued at the mark, so main-stream work enqueued between the two is
+// captured ahead of the side work (in a captured graph the main chain then
+// keeps its hardware queue) without the side work waiting for it.
 struct SideStream {
   hipStream_t stream;
   hipEvent_t ev[2];
@@ -282,6 +286,8 @@ struct SideStream {
 bool overlap_enabled();  // unless CPRA_OVERLAP=0 in the environment
 cpra_status get_side_stream(SideStream** out);
 cpra_status fork_to(SideStream* s, hipStream_t main);
+cpra_status fork_mark(SideStream* s, hipStream_t main);
+cpra_status fork_wait(SideStream* s);
 cpra_status join_from(SideStream* s, hipStream_t main);
 
 // The loss in two launches: the fused per-node kernel (dZ + per-item partials

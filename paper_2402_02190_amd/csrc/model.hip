@@ -212,6 +212,11 @@ bool wgrad_late() {
   return e != nullptr && e[0] == '1';
 }
 
+bool side_first_order() {
+  const char* e = getenv("CPRA_SIDE_FIRST");
+  return e != nullptr && e[0] == '1';
+}
+
 // The work queue of the aggregations on the main (0) or side (1) stream.
 inline int32_t* queue_of(void* ws, const Plan& p, int which) {
   return reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.q_off) + which * kQueueInts;
@@ -349,6 +354,17 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
     }
     return CPRA_OK;
   };
+  // Order of a layer's two halves after its fork.  By default the fork is
+  // marked, the input gradient (the main chain) enqueued, and only then the
+  // side work: in a captured graph the input gradient is then the first
+  // successor of the gather before it and keeps the main chain's hardware queue
+  // (a hop to another queue costs a dependency wait of several microseconds).
+  // CPRA_SIDE_FIRST=1 captures the side work first, which dispatches the weight
+  // gradients ahead of the input gradient they run beside.  (Mixing the two
+  // orders within one step let the graph launcher put independent kernels of
+  // both halves on one queue, in series.)
+  const bool side_first = side_first_order();
+  auto main_first = [&](int) { return side != nullptr && !side_first; };
   const float* dY = dZ;
   int64_t lddy = lddz;
   int ping = 0, tping = 0;
@@ -390,47 +406,72 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         CPRA_CHECK(before_write(dX));
         CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
       }
-      if (side) {
-        CPRA_CHECK(fork_to(side, st));
-        CPRA_CHECK(forked());
-        pending.add(dY);
-        pending.add(T);
+      if (side) CPRA_CHECK(fork_mark(side, st));
+      auto input_grad = [&]() -> cpra_status {
+        if (!need_dx || late) return CPRA_OK;
+        GemmProblem r{};
+        r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
+        r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
+        r.n_pieces = 2;
+        r.C = dX;
+        r.ldc = lddx;
+        r.M = N;
+        r.N = l.in;
+        r.mask = mask;
+        r.ld_mask = ldh;
+        set_groups(p, g, &rows, 1, &r, l);
+        CPRA_CHECK(before_write(dX));
+        return gemm_batch(false, false, &r, 1, nullptr, 0, st);
+      };
+      auto weight_grads = [&]() -> cpra_status {
+        if (side) {
+          CPRA_CHECK(fork_wait(side));
+          CPRA_CHECK(forked());
+          pending.add(dY);
+          pending.add(T);
+        }
+        GemmProblem q[2] = {};
+        for (int i = 0; i < 2; ++i) {
+          q[i].piece[0] = GemmPiece{i == 0 ? dY : T, Hk, i == 0 ? lddy : l.out, ldh, N};
+          q[i].n_pieces = 1;
+          q[i].C = i == 0 ? dWs : dWn;
+          q[i].ldc = l.in;
+          q[i].M = l.out;
+          q[i].N = l.in;
+          set_groups(p, g, &rows, 2, &q[i], l);
+        }
+        if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
+        return gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst);
+      };
+      if (main_first(k)) {
+        CPRA_CHECK(input_grad());
+        CPRA_CHECK(weight_grads());
+      } else {
+        CPRA_CHECK(weight_grads());
+        CPRA_CHECK(input_grad());
       }
-      GemmProblem q[2] = {};
-      for (int i = 0; i < 2; ++i) {
-        q[i].piece[0] = GemmPiece{i == 0 ? dY : T, Hk, i == 0 ? lddy : l.out, ldh, N};
-        q[i].n_pieces = 1;
-        q[i].C = i == 0 ? dWs : dWn;
-        q[i].ldc = l.in;
-        q[i].M = l.out;
-        q[i].N = l.in;
-        set_groups(p, g, &rows, 2, &q[i], l);
-      }
-      if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
-      CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
       if (!need_dx) break;
-      if (late) {
-        dY = dX;
-        lddy = lddx;
-        ping ^= 1;
-        continue;
-      }
-      GemmProblem r{};
-      r.piece[0] = GemmPiece{dY, Ws, lddy, l.in, l.out};
-      r.piece[1] = GemmPiece{T, Wn, l.out, l.in, l.out};
-      r.n_pieces = 2;
-      r.C = dX;
-      r.ldc = lddx;
-      r.M = N;
-      r.N = l.in;
-      r.mask = mask;
-      r.ld_mask = ldh;
-      set_groups(p, g, &rows, 1, &r, l);
-      CPRA_CHECK(before_write(dX));
-      CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
     } else {
+      float* G = fptr(ws, p.g_off);
+      const int64_t ldg = 2 * l.in;
+      if (side) CPRA_CHECK(fork_mark(side, st));
+      auto input_grad = [&]() -> cpra_status {  // G = dY [Ws | Wn]; the gather follows below
+        if (!need_dx) return CPRA_OK;
+        GemmProblem r[2] = {};
+        for (int i = 0; i < 2; ++i) {
+          r[i].piece[0] = GemmPiece{dY, i == 0 ? Ws : Wn, lddy, l.in, l.out};
+          r[i].n_pieces = 1;
+          r[i].C = G + (i == 0 ? 0 : l.in);
+          r[i].ldc = ldg;
+          r[i].M = N;
+          r[i].N = l.in;
+          set_groups(p, g, &rows, 1, &r[i], l);
+        }
+        return gemm_batch(false, false, r, 2, nullptr, 0, st);
+      };
+      if (main_first(k)) CPRA_CHECK(input_grad());
       if (side) {
-        CPRA_CHECK(fork_to(side, st));
+        CPRA_CHECK(fork_wait(side));
         CPRA_CHECK(forked());
         pending.add(dY);
       }
@@ -456,19 +497,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
       if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
       CPRA_CHECK(gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst));
       if (!need_dx) break;
-      float* G = fptr(ws, p.g_off);
-      const int64_t ldg = 2 * l.in;
-      GemmProblem r[2] = {};
-      for (int i = 0; i < 2; ++i) {
-        r[i].piece[0] = GemmPiece{dY, i == 0 ? Ws : Wn, lddy, l.in, l.out};
-        r[i].n_pieces = 1;
-        r[i].C = G + (i == 0 ? 0 : l.in);
-        r[i].ldc = ldg;
-        r[i].M = N;
-        r[i].N = l.in;
-        set_groups(p, g, &rows, 1, &r[i], l);
-      }
-      CPRA_CHECK(gemm_batch(false, false, r, 2, nullptr, 0, st));
+      if (!main_first(k)) CPRA_CHECK(input_grad());
       CPRA_CHECK(before_write(dX));
       CPRA_CHECK(aggregate(g, true, l.in, G + l.in, ldg, dX, lddx, G, ldg, nullptr, false, mask, ldh, st,
                            nullptr, 0, nullptr, 0, queue_of(ws, p, 0)));

@@ -53,6 +53,18 @@ cpra_status fork_to(SideStream* s, hipStream_t main) {
   return CPRA_OK;
 }
 
+cpra_status fork_mark(SideStream* s, hipStream_t main) {
+  const hipError_t e = hipEventRecord(s->ev[0], main);
+  if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "fork mark: %s", hipGetErrorString(e));
+  return CPRA_OK;
+}
+
+cpra_status fork_wait(SideStream* s) {
+  const hipError_t e = hipStreamWaitEvent(s->stream, s->ev[0], 0);
+  if (e != hipSuccess) CPRA_FAIL(CPRA_ERR_HIP, "fork wait: %s", hipGetErrorString(e));
+  return CPRA_OK;
+}
+
 cpra_status join_from(SideStream* s, hipStream_t main) {
   hipError_t e = hipEventRecord(s->ev[1], s->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(main, s->ev[1], 0);

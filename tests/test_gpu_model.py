@@ -387,6 +387,40 @@ def test_persistent_launches_are_bit_identical(preset, monkeypatch):
         assert torch.equal(x, y), name
 
 
+@pytest.mark.parametrize("preset", ["C2", "C3s", "C4"])
+def test_fork_orders_and_one_stream_are_bit_identical(preset, monkeypatch):
+    """The backward's two capture orders at each fork (the input gradient captured
+    ahead of the side-stream weight gradients, the default; the side work first,
+    CPRA_SIDE_FIRST=1) and the single-stream schedule (CPRA_OVERLAP=0) run the
+    same kernels on the same data, so three replayed training steps give the same
+    bits: GraphSAGE with bias gradients (C2), a ragged ER batch (C3s), and three
+    GCN layers whose transform buffers are reused across the backward (C4)."""
+    api, CPRAConfig, CPRASolver = mods()
+    pr = get_preset(preset)
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
+                     hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu, T=pr.T)
+    p = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=5)
+    out = {}
+    for name, env in (("main first", {}), ("side first", {"CPRA_SIDE_FIRST": "1"}),
+                      ("one stream", {"CPRA_OVERLAP": "0"})):
+        for k in ("CPRA_SIDE_FIRST", "CPRA_OVERLAP"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        say(f"  {preset}: {name}")
+        sol = CPRASolver(dg, cfg, pr.lam)
+        sol.load_params(p)
+        sol.run(3, use_graph=True)
+        torch.cuda.synchronize()
+        out[name] = [x.clone() for x in (sol.params, sol.Z, sol.dZ, sol.terms)]
+        sol.close()
+    for other in ("side first", "one stream"):
+        for what, x, y in zip(("params", "Z", "dZ", "terms"), out["main first"], out[other]):
+            assert torch.equal(x, y), f"{other}: {what}"
+
+
 def test_c1_end_to_end_against_oracle_and_exact_optimum():
     api, CPRAConfig, CPRASolver = mods()
     pr = get_preset("C1")

@@ -45,6 +45,7 @@ class Preset:
     nu: float = 0.0
     lr: float = 1e-3
     recompute: bool = False
+    side_first: bool = False  # capture each backward fork's side work first (CPRA_SIDE_FIRST=1)
     graph_fn: Callable[[], CSRGraph] = field(default=None, repr=False)
     description: str = ""
 
@@ -77,7 +78,7 @@ PRESETS: Dict[str, Preset] = {
         graph_fn=lambda: random_regular_graph(10_000, 5, seed=2),
         description="MIS on a random 5-regular graph, N=10000, 2-layer GraphSAGE hidden 256, S=100"),
     "C3": Preset(
-        "C3", "maxcut", "gcn", 2, 64, 32, None, -2.0, 0.1, 2000, nu=0.1,
+        "C3", "maxcut", "gcn", 2, 64, 32, None, -2.0, 0.1, 2000, nu=0.1, side_first=True,
         graph_fn=lambda: _c3_graph(256, seed=3),
         description="MaxCut on 256 Erdos-Renyi graphs (N~U{500..5000}, mean degree~U[4,10]), "
                     "2-layer GCN hidden 64, S=32, nu=0.1"),
