@@ -294,8 +294,9 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
         pmc_pass(sol, 5)
         sol.close()
         return None, (pr, g, params, W)
-    # warm-up: capture once, replay W steps
-    sol.capture()
+    # warm-up: capture once (one step, and args.graph_steps steps in a second graph),
+    # replay W steps
+    sol.capture(steps_per_graph=args.graph_steps)
     sol.replay(args.warmup)
     torch.cuda.synchronize()
     log(f"[bench] {workload}: warmup {args.warmup} steps done")
@@ -306,23 +307,30 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
     ev1 = torch.cuda.Event(enable_timing=True)
     # events at the ends of five equal chunks of the K steps (same stream, no sync):
     # the median chunk is reported beside the K-step figure
-    n_chunks = 5 if args.steps >= 5 else 1
-    bounds = [args.steps * c // n_chunks for c in range(n_chunks + 1)]
+    # (a chunk ends after the first launch that reaches its share of the steps)
+    plan = sol.launch_plan(args.steps)
+    n_chunks = 5 if len(plan) >= 5 else 1
+    targets = [args.steps * c // n_chunks for c in range(1, n_chunks)]
     chunk_ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks - 1)]
+    chunk_steps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for i in range(args.steps):
-        api.graph_launch(sol._graph, stream)
-        if i + 1 in bounds[1:-1]:
-            chunk_ev[bounds.index(i + 1) - 1].record(stream)
+    done = 0
+    for gr, ns in plan:
+        api.graph_launch(gr, stream)
+        done += ns
+        if len(chunk_steps) < n_chunks - 1 and done >= targets[len(chunk_steps)]:
+            chunk_ev[len(chunk_steps)].record(stream)
+            chunk_steps.append(done)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sol.t += args.steps
     ms_event = ev0.elapsed_time(ev1) / args.steps
     marks = [ev0] + chunk_ev + [ev1]
-    chunk_ms = sorted(marks[c].elapsed_time(marks[c + 1]) / (bounds[c + 1] - bounds[c])
+    ends = [0] + chunk_steps + [args.steps]
+    chunk_ms = sorted(marks[c].elapsed_time(marks[c + 1]) / (ends[c + 1] - ends[c])
                       for c in range(n_chunks))
     ms_median_chunk = chunk_ms[n_chunks // 2]
     ms_per_step = wall * 1e3 / args.steps
@@ -347,7 +355,8 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
                    "problem": pr.problem, "recompute": bool(pr.recompute),
                    "backward_fork_order": "side work first" if pr.side_first else "input gradient first",
-                   "hip_graph_replay": True, "per_graph_weights": bool(per_graph),
+                   "hip_graph_replay": True, "steps_per_graph": args.graph_steps,
+                   "per_graph_weights": bool(per_graph),
                    "autotuned_gemm": not args.no_autotune,
                    "ms_per_step_events": ms_event,
                    "ms_per_step_median_of_5_chunks": ms_median_chunk},
@@ -419,6 +428,9 @@ def main():
     ap.add_argument("--tuning-file", default=None,
                     help="GEMM tuning table: loaded if it exists, else written after autotuning "
                          "(default: the committed MI355X table of the workload, if any)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="training steps recorded in one HIP graph for the replays (one graph "
+                         "launch per that many steps; a one-step graph runs the remainder)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run only the short sequence the HBM counter passes profile")
     ap.add_argument("--loss-sweep", type=int, nargs="*", default=None, metavar="N",

@@ -123,6 +123,7 @@ class CPRASolver:
         self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
         self.t = 0
         self._graph = None
+        self._graph_k = None  # (graph of k consecutive steps, k), k > 1
         self._stream = None
 
     def set_reuse_frozen_prefix(self, on: bool) -> None:
@@ -215,33 +216,56 @@ class CPRASolver:
             table = api.autotune_end()
         return table
 
-    def capture_step(self):
-        """Record one training step into a new HIP graph on the solver's private
-        stream and return its handle (the caller destroys it)."""
+    def capture_step(self, steps: int = 1):
+        """Record `steps` consecutive training steps into a new HIP graph on the
+        solver's private stream and return its handle (the caller destroys it).
+        Adam's step index comes from the device step counter, which every step
+        advances, so the recorded steps are the same step repeated."""
         if self._stream is None:
             self._stream = torch.cuda.Stream()
         self._stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self._stream):
             api.capture_begin(self._stream)
             try:
-                api.train_step(self.graph, self.step_cfg, self.params, self.grads, self.m, self.v,
-                               self.Z, self.dZ, self.terms, self.ws, 1, self.step_counter,
-                               self._stream)
+                for _ in range(steps):
+                    api.train_step(self.graph, self.step_cfg, self.params, self.grads, self.m,
+                                   self.v, self.Z, self.dZ, self.terms, self.ws, 1,
+                                   self.step_counter, self._stream)
             finally:
                 g = api.capture_end(self._stream)
         return g
 
-    def capture(self) -> None:
-        """Record one training step into the solver's HIP graph (once)."""
+    def capture(self, steps_per_graph: int = 1) -> None:
+        """Record one training step into the solver's HIP graph (once) and, with
+        steps_per_graph = k > 1, also k consecutive steps into a second graph:
+        replays then launch one graph per k steps, which saves the idle time
+        between two launches of a graph (several microseconds each) inside
+        the k steps."""
         if self._graph is None:
             self._graph = self.capture_step()
+        if steps_per_graph > 1 and (self._graph_k is None or self._graph_k[1] != steps_per_graph):
+            if self._graph_k is not None:
+                api.graph_destroy(self._graph_k[0])
+                self._graph_k = None
+            self._graph_k = (self.capture_step(steps_per_graph), steps_per_graph)
 
-    def replay(self, n: int = 1) -> None:
+    def launch_plan(self, n: int):
+        """The graph launches that replay n steps: [(graph, steps it runs), ...],
+        the k-step graph as often as it fits, then the one-step graph."""
         if self._graph is None:
             self.capture()
+        plan = []
+        if self._graph_k is not None:
+            gk, k = self._graph_k
+            plan += [(gk, k)] * (n // k)
+            n -= (n // k) * k
+        return plan + [(self._graph, 1)] * n
+
+    def replay(self, n: int = 1) -> None:
+        plan = self.launch_plan(n)
         self._stream.wait_stream(torch.cuda.current_stream())
-        for _ in range(n):
-            api.graph_launch(self._graph, self._stream)
+        for g, _ in plan:
+            api.graph_launch(g, self._stream)
         torch.cuda.current_stream().wait_stream(self._stream)
         self.t += n
 
@@ -362,6 +386,9 @@ class CPRASolver:
         if self._graph is not None:
             api.graph_destroy(self._graph)
             self._graph = None
+        if self._graph_k is not None:
+            api.graph_destroy(self._graph_k[0])
+            self._graph_k = None
 
     def __del__(self):
         try:

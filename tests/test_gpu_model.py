@@ -421,6 +421,33 @@ def test_fork_orders_and_one_stream_are_bit_identical(preset, monkeypatch):
             assert torch.equal(x, y), f"{other}: {what}"
 
 
+def test_multi_step_graph_replays_equal_one_step_replays():
+    """Ten steps replayed through a graph of four recorded steps (two launches, then
+    two launches of the one-step graph) give the same bits as ten one-step
+    replays: the steps of a graph take Adam's index and the annealing weight from
+    the device step counter like separate launches do."""
+    api, CPRAConfig, CPRASolver = mods()
+    pr = get_preset("C3s")
+    g = pr.graph()
+    dg = api.DeviceGraph.from_csr(g)
+    cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
+                     hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu, T=pr.T)
+    p = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=9)
+    out = []
+    for k in (1, 4):
+        sol = CPRASolver(dg, cfg, pr.lam)
+        sol.load_params(p)
+        sol.capture(steps_per_graph=k)
+        assert [n for _, n in sol.launch_plan(10)] == ([1] * 10 if k == 1 else [4, 4, 1, 1])
+        sol.replay(10)
+        torch.cuda.synchronize()
+        out.append([x.clone() for x in (sol.params, sol.m, sol.v, sol.Z, sol.terms, sol.step_counter)])
+        sol.close()
+    for what, x, y in zip(("params", "m", "v", "Z", "terms", "step counter"), *out):
+        assert torch.equal(x, y), what
+    assert int(out[1][5].item()) == 10
+
+
 def test_c1_end_to_end_against_oracle_and_exact_optimum():
     api, CPRAConfig, CPRASolver = mods()
     pr = get_preset("C1")
