@@ -379,6 +379,14 @@ struct DmaTile {
     const unsigned o = KCONTIG ? off[pc][v] + (unsigned)k0 : off[pc][v] + (unsigned)k0 * (unsigned)ld;
     return (4u * o) | ((ok ^ 1u) << 31);
   }
+  // Element (row or column mn, k) of a stage.
+  __device__ static inline float at(const float* Xs, int mn, int k) {
+    if constexpr (KCONTIG) {
+      return Xs[mn * BK + 4 * RowK::chunk_at(mn, k / 4) + k % 4];
+    } else {
+      return Xs[k * R + (mn ^ (32 * ((k / (BK / 2)) & 1)))];
+    }
+  }
   // Read q of the operands of row or column mn for half-wavefront h:
   // v[kk] for k = h * BK/2 + kk.
   template <int q>
@@ -560,6 +568,7 @@ void k_gemm(LaunchArgs args) {
   const bool do_bias = bgrad_g != nullptr && tn_idx == 0;
   const int b_row = tid % BM, b_grp = tid / BM;
   float bsum = 0.f;
+  float* bias_red = nullptr;  // LDS for the bias sums' reduction (the ring loop's first stage)
 
   // multiply the tile staged in LDS buffer `cur` (and add its A rows for the bias)
   auto compute = [&](int cur) {
@@ -762,7 +771,10 @@ void k_gemm(LaunchArgs args) {
     // loads of a later tile before an operand read.  The barrier is a plain
     // s_barrier: a workgroup fence would wait for every load in flight.
     // Past the last tile the loads re-read it into stages never read again.
-    // No bias gradient here (the launcher gives such problems another loop).
+    // Bias gradient: every thread adds its slice of each A tile (rows b_row, k
+    // rows b_grp * BK/BG ..) from the stage while it reads the tile's operands,
+    // a tile past the last one contributing zeros (bit mask, no branch); only
+    // the first column tile's blocks store the sums.
     using DA = DmaTile<BM, BK, NT, !A_T>;
     using DB = DmaTile<BN, BK, NT, B_T>;
     constexpr int D = 4;
@@ -789,8 +801,13 @@ void k_gemm(LaunchArgs args) {
       float b[TN][BK / 2];
     };
     constexpr int NRA = TM * DA::NREAD, NRB = TN * DB::NREAD;
-    constexpr int NOPS = NL + NRA + NRB;
+    constexpr int NBIAS = BK / BG;  // bias reads per thread and tile
+    constexpr int NOPS = NL + NRA + NRB + NBIAS;
     constexpr int NSLOT = (BK / 2) * TM * TN;
+    auto bias_add = [&](const float* st, int q, unsigned keep) {
+      const float x = DA::at(st, b_row, b_grp * NBIAS + q);
+      bsum += __uint_as_float(__float_as_uint(x) & keep);
+    };
     DA da;
     DB db;
     da.setup(lda0, lda1, m0, m_lim, tid);
@@ -846,6 +863,7 @@ void k_gemm(LaunchArgs args) {
       using StNext = std::integral_constant<int, (ph + 1) % D>;
       sync(std::integral_constant<int, (D - 2) * NL>{});
       const TileRef t = tile_ref(min(kt + D, kt_end - 1));
+      const unsigned keep_next = 0u - (unsigned)(kt + 1 < kt_end);  // tile kt + 1 exists
       static_for<NSLOT>([&](auto sc) {
         constexpr int sl = decltype(sc)::value;
         constexpr int kk = sl / (TM * TN), i = (sl / TN) % TM, j = sl % TN;
@@ -859,10 +877,12 @@ void k_gemm(LaunchArgs args) {
               constexpr int r = o - NL;
               DA::template read_part<r % DA::NREAD>(stage_a(StNext{}), (wm * TM + r / DA::NREAD) * 32 + l32,
                                                     half, nxf.a[r / DA::NREAD]);
-            } else {
+            } else if constexpr (o < NL + NRA + NRB) {
               constexpr int r = o - NL - NRA;
               DB::template read_part<r % DB::NREAD>(stage_b(StNext{}), (wn * TN + r / DB::NREAD) * 32 + l32,
                                                     half, nxf.b[r / DB::NREAD]);
+            } else {
+              bias_add(stage_a(StNext{}), o - NL - NRA - NRB, keep_next);
             }
           }
         });
@@ -874,6 +894,7 @@ void k_gemm(LaunchArgs args) {
       static_for<D>([&](auto st) { load_all(st, min(kt_begin + decltype(st)::value, kt_end - 1)); });
       sync(std::integral_constant<int, (D - 1) * NL>{});
       read_all(std::integral_constant<int, 0>{}, f0);
+      for (int q = 0; q < NBIAS; ++q) bias_add(Sa0, q, ~0u);
       int kt = kt_begin;
       for (; kt + D <= kt_end; kt += D) {
         static_for<D>([&](auto ph) {
@@ -892,6 +913,7 @@ void k_gemm(LaunchArgs args) {
       // the loads past the last tile land before the block may leave its LDS
       __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
     }
+    bias_red = Sa0;
   }
 
   // Accumulator layout of the 32x32 MFMA: register r of lane l holds
@@ -919,17 +941,21 @@ void k_gemm(LaunchArgs args) {
       }
     });
   });
-  if constexpr (PF != 4) {
-    if (do_bias) {  // fixed-order sum of the BG slices of each row (As is free after the loop)
-      float* red = As[0];
-      if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
-      __syncthreads();
-      if (tid < BM && m0 + tid < m_lim) {
-        float v = 0.f;
-        for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
-        if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
-        else bgrad_g[m0 + tid] = v;
-      }
+  if (do_bias) {  // fixed-order sum of the BG slices of each row
+    float* red;
+    if constexpr (PF == 4) {
+      red = bias_red;
+      __syncthreads();  // every wave is past its last read of the ring and its loads have landed
+    } else {
+      red = As[0];  // free after the loop
+    }
+    if (b_grp < BG) red[b_grp * BM + b_row] = bsum;
+    __syncthreads();
+    if (tid < BM && m0 + tid < m_lim) {
+      float v = 0.f;
+      for (int g2 = 0; g2 < BG; ++g2) v += red[g2 * BM + tid];
+      if (partial) part[(int64_t)(m0 + tid) * P.n_eff + P.N] = v;
+      else bgrad_g[m0 + tid] = v;
     }
   }
 }
@@ -970,8 +996,7 @@ constexpr Cfg kCfgs[] = {
     {64, 128, 16, 2, 2},   // 24
     {64, 64, 32, 2, 2},    // 25
     {64, 128, 32, 2, 2},   // 26
-    // LDS ring (tiles written to LDS by the loads, three steps ahead); not for
-    // products with a bias gradient
+    // LDS ring (tiles written to LDS by the loads, three steps ahead)
     {64, 64, 16, 2, 2},    // 27
     {64, 128, 16, 2, 2},   // 28
     {128, 64, 16, 2, 2},   // 29
@@ -1037,10 +1062,10 @@ inline bool pf2_ok(const LaunchArgs& args, bool a_t, bool b_t) {
 // one-deep configuration standing in for a two-deep one (similar tile shape)
 constexpr int kPf1Twin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 6, 0, 3, 4, 7, 9, 8, 2, 1, 3,
                             6, 7, 3, 7, 4, 0, 4, 6, 4, 3, 0, 7};
-// two-deep configuration standing in for an interleaved or LDS-ring one where a
-// problem wants a bias gradient
+// two-deep configuration standing in for an interleaved one where a problem
+// wants a bias gradient (the LDS-ring ones compute it themselves)
 constexpr int kIlTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
-                           10, 14, 12, 14, 13, 11, 13, 10, 13, 12, 11, 14};
+                           10, 14, 12, 14, 13, 11, 13, 27, 28, 29, 30, 31};
 // interleaved configuration standing in for an LDS-ring one whose operands
 // reach past the 2^31-byte offsets of its buffer loads
 constexpr int kRingTwin[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,

@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import (assert_close_array, assert_close_scalar, assert_update_close, check_relu_decisions,
-                     need_gpu, say, to_dev)
+from helpers import (N_GEMM_CFGS, assert_close_array, assert_close_scalar, assert_update_close,
+                     check_relu_decisions, need_gpu, say, to_dev)
 from oracle import evaluate as oev
 from oracle import exact as oexact
 from oracle import gnn as ognn
@@ -486,13 +486,16 @@ def test_c1_end_to_end_against_oracle_and_exact_optimum():
     assert agree >= 0.9
 
 
-@pytest.mark.parametrize("cfg", range(20))
+@pytest.mark.parametrize("cfg", range(N_GEMM_CFGS))
 def test_sage_bias_gradient_under_every_weight_gradient_plan(cfg):
     """The bias gradient is summed inside the weight-gradient GEMM by the first
     column tile: check db (and dWs) of a 2-layer SAGE model with every tile
-    configuration forced on those GEMMs, with and without split-K.  The same
-    configuration is forced on the step's other products too (the two-piece
-    [X | MX] forward and the input gradients), and every gradient is checked."""
+    configuration forced on those GEMMs, with and without split-K (150 splits
+    leave some splits without a K tile, whose partial sums must be zeros).  The
+    interleaved configurations run their two-deep twins for it, the LDS-ring
+    ones sum the bias from their stages.  The same configuration is forced on
+    the step's other products too (the two-piece [X | MX] forward and the input
+    gradients), and every gradient is checked."""
     api, CPRAConfig, CPRASolver = mods()
     g = random_regular_graph(700, 5, 9)
     dg = api.DeviceGraph.from_csr(g)
