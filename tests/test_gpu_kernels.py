@@ -442,10 +442,10 @@ def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
         a.autotune_reset()
 
 
-@pytest.mark.parametrize("M,cfg,splits", [(32, 16, 1024), (64, 27, 512), (64, 11, 512)])
+@pytest.mark.parametrize("M,cfg,splits", [(32, 27, 1024), (64, 27, 512), (32, 16, 1024), (64, 11, 512)])
 def test_gemm_committed_large_split_plans(M, cfg, splits):
     """The split-K plans of the committed 256-graph tuning table at their real shape
-    (and the two-deep plan the LDS ring replaced): weight gradients A^T B over
+    (and the two-deep plans the LDS ring replaced): weight gradients A^T B over
     K = 710,241 rows in 1,024 and 512 splits, summed in a fixed order."""
     a = api()
     N, K = 64, 710241
