@@ -771,10 +771,12 @@ void k_gemm(LaunchArgs args) {
     // loads of a later tile before an operand read.  The barrier is a plain
     // s_barrier: a workgroup fence would wait for every load in flight.
     // Past the last tile the loads re-read it into stages never read again.
-    // Bias gradient: every thread adds its slice of each A tile (rows b_row, k
-    // rows b_grp * BK/BG ..) from the stage while it reads the tile's operands,
-    // a tile past the last one contributing zeros (bit mask, no branch); only
-    // the first column tile's blocks store the sums.
+    // Bias gradient: in the blocks that store one (the first column tile of a
+    // problem that wants it; a uniform branch), every thread adds its slice of
+    // each A tile (row b_row, k rows b_grp * BK/BG ..) from the stage while it
+    // reads the tile's operands, a tile past the last one contributing zeros
+    // (bit mask).  Other blocks skip the reads, which on a K-contiguous A tile
+    // would meet bank conflicts.
     using DA = DmaTile<BM, BK, NT, !A_T>;
     using DB = DmaTile<BN, BK, NT, B_T>;
     constexpr int D = 4;
@@ -882,7 +884,7 @@ void k_gemm(LaunchArgs args) {
               DB::template read_part<r % DB::NREAD>(stage_b(StNext{}), (wn * TN + r / DB::NREAD) * 32 + l32,
                                                     half, nxf.b[r / DB::NREAD]);
             } else {
-              bias_add(stage_a(StNext{}), o - NL - NRA - NRB, keep_next);
+              if (do_bias) bias_add(stage_a(StNext{}), o - NL - NRA - NRB, keep_next);
             }
           }
         });
@@ -894,7 +896,8 @@ void k_gemm(LaunchArgs args) {
       static_for<D>([&](auto st) { load_all(st, min(kt_begin + decltype(st)::value, kt_end - 1)); });
       sync(std::integral_constant<int, (D - 1) * NL>{});
       read_all(std::integral_constant<int, 0>{}, f0);
-      for (int q = 0; q < NBIAS; ++q) bias_add(Sa0, q, ~0u);
+      if (do_bias)
+        for (int q = 0; q < NBIAS; ++q) bias_add(Sa0, q, ~0u);
       int kt = kt_begin;
       for (; kt + D <= kt_end; kt += D) {
         static_for<D>([&](auto ph) {
