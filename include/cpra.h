@@ -359,12 +359,7 @@ cpra_status cpra_adam_step(int64_t n, float* params, const float* grads, float* 
  * reduction run on a library-owned second stream of the current device,
  * forked from and joined back into `stream` by events (also when captured);
  * CPRA_OVERLAP=0 in the environment (read at every call) keeps all work on
- * `stream`.  Also read at every call: CPRA_SIDE_FIRST=1 enqueues each fork's
- * second-stream work ahead of the layer's input gradient (the default is the
- * other order); CPRA_FUSED_EMB_ADAM=1 (cpra_train_step) applies Adam to the
- * embedding in the epilogue of the product that emits its gradient when layer
- * 0 is transform-first, after that layer's weight gradients on `stream`.  Both
- * give the same results as the defaults.
+ * `stream`.
  * cpra_model_backward overlaps its weight gradients the same way.
  * ---------------------------------------------------------------------- */
 /* ------------------------------------------------------------------------

@@ -26,6 +26,19 @@ struct AdamArgs {
   const int32_t* stop_flag;  // optional: no update while *stop_flag != 0 (early stopping)
 };
 
+struct AdamCoef {
+  float lr, b1, omb1, b2, omb2, eps, decay;
+};
+
+__device__ inline void adam_one(float& p, float g, float& m, float& v, const AdamCoef& c,
+                                float inv_bc1, float inv_sqrt_bc2) {
+  m = c.b1 * m + c.omb1 * g;
+  v = c.b2 * v + c.omb2 * g * g;
+  const float mhat = m * inv_bc1;
+  const float denom = sqrtf(v) * inv_sqrt_bc2 + c.eps;  // sqrt(v / bc2) + eps
+  p = p * c.decay - c.lr * mhat / denom;
+}
+
 template <bool VEC4>
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   if (a.stop_flag && *a.stop_flag) return;  // uniform across the grid
@@ -89,23 +102,6 @@ cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, fl
     hipLaunchKernelGGL(k_adam<false>, dim3(blocks), dim3(256), 0, stream, a);
   CPRA_CHECK_LAUNCH("adam");
   return CPRA_OK;
-}
-
-AdamEpi adam_epi(const cpra_adam_cfg* cfg, float* params, float* m, float* v, int t,
-                 const int32_t* step_counter, int t_offset, const int32_t* stop_flag) {
-  AdamEpi a{};
-  a.p = params;
-  a.m = m;
-  a.v = v;
-  a.c = AdamCoef{(float)cfg->lr, (float)cfg->beta1, (float)(1.0 - cfg->beta1), (float)cfg->beta2,
-                 (float)(1.0 - cfg->beta2), (float)cfg->eps, (float)(1.0 - cfg->lr * cfg->weight_decay)};
-  a.b1d = cfg->beta1;
-  a.b2d = cfg->beta2;
-  a.t = t;
-  a.step_counter = step_counter;
-  a.t_offset = t_offset;
-  a.stop_flag = stop_flag;
-  return a;
 }
 
 cpra_status check_adam_cfg(const cpra_adam_cfg* cfg) {

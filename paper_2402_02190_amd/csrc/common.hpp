@@ -201,48 +201,6 @@ cpra_status group_rows_build(const cpra_csr* g, void* ws, GroupRows* out, hipStr
 // The maps that group_rows_build wrote into ws earlier (no launch).
 cpra_status group_rows_view(const cpra_csr* g, void* ws, GroupRows* out);
 
-// Adam's element update (Sec. 4.1; Kingma & Ba, decoupled decay), shared by
-// the Adam pass and the GEMM epilogue that applies it to the parameters whose
-// gradient the product emits.  FP32 state; inv_bc1 = 1 / (1 - b1^t) and
-// inv_sqrt_bc2 = 1 / sqrt(1 - b2^t) are formed in FP64 by adam_corrections.
-struct AdamCoef {
-  float lr, b1, omb1, b2, omb2, eps, decay;
-};
-__device__ inline void adam_one(float& p, float g, float& m, float& v, const AdamCoef& c,
-                                float inv_bc1, float inv_sqrt_bc2) {
-  m = c.b1 * m + c.omb1 * g;
-  v = c.b2 * v + c.omb2 * g * g;
-  const float mhat = m * inv_bc1;
-  const float denom = sqrtf(v) * inv_sqrt_bc2 + c.eps;  // sqrt(v / bc2) + eps
-  p = p * c.decay - c.lr * mhat / denom;
-}
-
-// Adam in a GEMM epilogue: after C[row, col] = g is stored, the parameter,
-// first and second moment at p/m/v[row * ldc + col] take Adam's update with g.
-struct AdamEpi {
-  float* p;
-  float* m;
-  float* v;
-  AdamCoef c;
-  double b1d, b2d;
-  int t;                        // step index when step_counter is null
-  const int32_t* step_counter;  // else t = *step_counter + t_offset, read on the device
-  int t_offset;
-  const int32_t* stop_flag;     // optional: no update while *stop_flag != 0 (early stopping)
-};
-AdamEpi adam_epi(const cpra_adam_cfg* cfg, float* params, float* m, float* v, int t,
-                 const int32_t* step_counter, int t_offset, const int32_t* stop_flag);
-// The bias corrections of the step (false: no update, the rule has stopped).
-__device__ inline bool adam_corrections(const AdamEpi& a, float* inv_bc1, float* inv_sqrt_bc2) {
-  if (a.stop_flag && *a.stop_flag) return false;
-  const int t = a.step_counter ? (*a.step_counter + a.t_offset) : a.t;
-  const double bc1 = 1.0 - pow(a.b1d, (double)t);
-  const double bc2 = 1.0 - pow(a.b2d, (double)t);
-  *inv_bc1 = (float)(1.0 / bc1);
-  *inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
-  return true;
-}
-
 struct GemmProblem {
   GemmPiece piece[2];  // the contraction runs over piece[0].K then piece[1].K
   int n_pieces;
@@ -270,10 +228,6 @@ struct GemmProblem {
   const int32_t* group_ptr;  // [n_groups + 1] graph row offsets (device; mode 2)
   const GroupRows* rows;     // row tiles (mode 1)
   int64_t b_stride, c_stride, bias_stride, bg_stride;
-  // Optional: Adam applied to the parameters at C's element indices after C is
-  // stored (C the gradient; beta 0).  The problems of a launch that carry it
-  // share its coefficients.
-  const AdamEpi* adam;
 };
 
 // Up to 4 independent problems in one launch, all with the same operand layout.

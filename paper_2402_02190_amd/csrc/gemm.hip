@@ -76,10 +76,7 @@ __global__ __launch_bounds__(kRedElems * kRedGroups) void k_gemm_splitk_reduce(L
     return;
   }
   if (P.bias) v += P.bias[col];
-  const float gv = epilogue_store(P, P.C + (int64_t)g * P.c_stride, row, col, v);
-  float inv_bc1, inv_sqrt_bc2;
-  if (P.adam_p && adam_corrections(args.adam, &inv_bc1, &inv_sqrt_bc2))
-    epilogue_adam(P, args.adam, row, col, gv, inv_bc1, inv_sqrt_bc2);
+  epilogue_store(P, P.C + (int64_t)g * P.c_stride, row, col, v);
 }
 
 inline bool vec_ok(const float* p, int64_t ld) {
@@ -272,12 +269,6 @@ void fill_args(const GemmProblem* probs, int n, int splits, void* ws, LaunchArgs
     d.beta = q.beta;
     d.relu = q.relu;
     d.bias_grad = q.bias_grad;
-    if (q.adam) {
-      d.adam_p = q.adam->p;
-      d.adam_m = q.adam->m;
-      d.adam_v = q.adam->v;
-      args->adam = *q.adam;
-    }
     d.sig_out = q.sig_out;
     d.add = q.add;
     d.ld_add = q.ld_add;
@@ -438,24 +429,10 @@ cpra_status gemm_batch(bool a_t, bool b_t, const GemmProblem* probs_in, int n, v
         hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
     bool overwrite_only = true;  // tuning re-runs the GEMM: only if C is overwritten
     for (int i = 0; i < n; ++i) overwrite_only = overwrite_only && probs[i].beta == 0.f;
-    bool with_adam = false;
-    for (int i = 0; i < n; ++i) with_adam = with_adam || probs[i].adam != nullptr;
-    if (g_tuning && !capturing && overwrite_only && !with_adam)
+    if (g_tuning && !capturing && overwrite_only)
       return tune(a_t, b_t, probs, n, can_split ? ws : nullptr, can_split ? ws_bytes : 0, stream,
                   key, &pl);
-    if (g_tuning && !capturing && overwrite_only) {
-      // the tuner re-runs the product, so it times it without the epilogue's Adam
-      // update; the chosen plan then runs once with it (below)
-      GemmProblem plain[kMaxProblems];
-      for (int i = 0; i < n; ++i) {
-        plain[i] = probs[i];
-        plain[i].adam = nullptr;
-      }
-      CPRA_CHECK(tune(a_t, b_t, plain, n, can_split ? ws : nullptr, can_split ? ws_bytes : 0, stream,
-                      key, &pl));
-    } else {
-      pl = heuristic_plan(probs, n, can_split);
-    }
+    pl = heuristic_plan(probs, n, can_split);
   }
   // A tuned plan may split more than this workspace allows: fall back to fewer splits.
   // Row-grouped products are never split (their reduction has no per-graph bias).

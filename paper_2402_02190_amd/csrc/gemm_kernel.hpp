@@ -81,9 +81,6 @@ struct ProbDev {
   int n_eff;         // N + 1 when bias_grad is set
   int tiles_m, tiles_n;
   int64_t part_off;  // float offset of this problem's split-K partials
-  float* adam_p;     // non-null: Adam on adam_p/m/v at C's element indices (LaunchArgs::adam)
-  float* adam_m;
-  float* adam_v;
 };
 
 struct LaunchArgs {
@@ -98,7 +95,6 @@ struct LaunchArgs {
   const int4* row_map;     // mode 1: per row tile {graph, first row, end row, 0}; graph -1: none
   const int4* row_maps[3];  // the maps for BM = 32, 64, 128 (the launcher picks row_map)
   int row_counts[3];
-  AdamEpi adam;             // coefficients of the epilogue's Adam update (its p/m/v unused)
 };
 
 // One operand tile (R rows or columns of the output by BK steps of K) in LDS,
@@ -417,9 +413,8 @@ __device__ inline void load_lds16(const float* base, float* lds, unsigned voff) 
 // count unchecked (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | (7 << 4) | ((vm >> 4) << 14); }
 
-// C[row, col] = mask(relu(v + add + beta C)) and optionally sigmoid(C) into
-// sig_out; returns the stored value.
-__device__ inline float epilogue_store(const ProbDev& P, float* C, int row, int col, float v) {
+// C[row, col] = mask(relu(v + add + beta C)) and optionally sigmoid(C) into sig_out.
+__device__ inline void epilogue_store(const ProbDev& P, float* C, int row, int col, float v) {
   float* cp = C + (int64_t)row * P.ldc + col;
   if (P.add) v += P.add[(int64_t)row * P.ld_add + col];
   if (P.beta != 0.f) v += P.beta * *cp;
@@ -431,14 +426,6 @@ __device__ inline float epilogue_store(const ProbDev& P, float* C, int row, int 
     const float r = 1.0f / (1.0f + e);
     P.sig_out[(int64_t)row * P.ld_sig + col] = v >= 0.0f ? r : e * r;
   }
-  return v;
-}
-
-// Adam on the parameter of C[row, col] whose gradient g was just stored.
-__device__ inline void epilogue_adam(const ProbDev& P, const AdamEpi& a, int row, int col, float g,
-                                     float inv_bc1, float inv_sqrt_bc2) {
-  const int64_t i = (int64_t)row * P.ldc + col;
-  adam_one(P.adam_p[i], g, P.adam_m[i], P.adam_v[i], a.c, inv_bc1, inv_sqrt_bc2);
 }
 
 // A_T: A stored [K, M] (M contiguous); otherwise [M, K].
@@ -939,9 +926,6 @@ void k_gemm(LaunchArgs args) {
   float* part = partial
                     ? args.partial + P.part_off + ((int64_t)split * GE + grp) * P.M * P.n_eff
                     : nullptr;
-  float inv_bc1 = 0.f, inv_sqrt_bc2 = 0.f;
-  const bool adam_now =
-      !partial && P.adam_p != nullptr && adam_corrections(args.adam, &inv_bc1, &inv_sqrt_bc2);
   static_for<TM>([&](auto i) {
     static_for<TN>([&](auto j) {
       const int col = n0 + (wn * TN + j) * 32 + l32;
@@ -955,8 +939,7 @@ void k_gemm(LaunchArgs args) {
         if (partial) {
           part[(int64_t)row * P.n_eff + col] = v;
         } else {
-          const float g = epilogue_store(P, Cg, row, col, v + bv);
-          if (adam_now) epilogue_adam(P, args.adam, row, col, g, inv_bc1, inv_sqrt_bc2);
+          epilogue_store(P, Cg, row, col, v + bv);
         }
       }
     });

@@ -217,11 +217,6 @@ bool side_first_order() {
   return e != nullptr && e[0] == '1';
 }
 
-bool fused_emb_adam_enabled() {
-  const char* e = getenv("CPRA_FUSED_EMB_ADAM");
-  return e != nullptr && e[0] == '1';
-}
-
 // The work queue of the aggregations on the main (0) or side (1) stream.
 inline int32_t* queue_of(void* ws, const Plan& p, int which) {
   return reinterpret_cast<int32_t*>(static_cast<char*>(ws) + p.q_off) + which * kQueueInts;
@@ -329,16 +324,10 @@ struct PendingReads {
 // by the forward of the same step).  side_task (optional, with a side stream):
 // work enqueued on the side stream right after the first fork -- the
 // training step's loss-term reduction, so that it needs no fork of its own.
-// emb_adam (optional): Adam for the embedding, applied in the epilogue of the
-// product that emits its gradient when layer 0 is transform-first (*emb_adam_done
-// then set).  That layer's weight gradients, which read the embedding, run
-// before it on the caller's stream, after a join that also settles the step
-// counter and the stopping flag (advanced by the side task).
 cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params, const float* dZ,
                           int64_t lddz, float* grads, void* ws, hipStream_t st,
                           SideStream* side, bool rows_ready,
-                          const std::function<cpra_status(hipStream_t)>* side_task = nullptr,
-                          const AdamEpi* emb_adam = nullptr, bool* emb_adam_done = nullptr) {
+                          const std::function<cpra_status(hipStream_t)>* side_task = nullptr) {
   const int N = g->n_nodes;
   GroupRows rows{};
   if (p.G > 1) {
@@ -417,20 +406,7 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         CPRA_CHECK(before_write(dX));
         CPRA_CHECK(gemm_batch(false, false, &r, 1, nullptr, 0, st));
       }
-      // embedding Adam in the input gradient's epilogue (layer 0 only)
-      const bool fuse_adam = emb_adam != nullptr && k == 0 && need_dx && !late;
-      if (fuse_adam) {
-        if (side_task && *side_task) {  // one-layer model: the side task has not run yet
-          CPRA_CHECK((*side_task)(st));
-          side_task = nullptr;
-        }
-        if (side) {
-          CPRA_CHECK(join_from(side, st));
-          pending.clear();
-        }
-      }
-      const hipStream_t lst = fuse_adam ? st : wst;  // stream of this layer's weight gradients
-      if (side && !fuse_adam) CPRA_CHECK(fork_mark(side, st));
+      if (side) CPRA_CHECK(fork_mark(side, st));
       auto input_grad = [&]() -> cpra_status {
         if (!need_dx || late) return CPRA_OK;
         GemmProblem r{};
@@ -443,13 +419,12 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
         r.N = l.in;
         r.mask = mask;
         r.ld_mask = ldh;
-        r.adam = fuse_adam ? emb_adam : nullptr;
         set_groups(p, g, &rows, 1, &r, l);
         CPRA_CHECK(before_write(dX));
         return gemm_batch(false, false, &r, 1, nullptr, 0, st);
       };
       auto weight_grads = [&]() -> cpra_status {
-        if (side && !fuse_adam) {
+        if (side) {
           CPRA_CHECK(fork_wait(side));
           CPRA_CHECK(forked());
           pending.add(dY);
@@ -466,16 +441,15 @@ cpra_status backward_impl(const cpra_csr* g, const Plan& p, const float* params,
           set_groups(p, g, &rows, 2, &q[i], l);
         }
         if (p.sage) q[0].bias_grad = grads + l.off_b;  // db = dY^T 1
-        return gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, lst);
+        return gemm_batch(true, false, q, 2, gemm_ws, p.gemm_bytes, wst);
       };
-      if (main_first(k) && !fuse_adam) {
+      if (main_first(k)) {
         CPRA_CHECK(input_grad());
         CPRA_CHECK(weight_grads());
-      } else {  // the weight gradients read the embedding before the fused update
+      } else {
         CPRA_CHECK(weight_grads());
         CPRA_CHECK(input_grad());
       }
-      if (fuse_adam && emb_adam_done) *emb_adam_done = true;
       if (!need_dx) break;
     } else {
       float* G = fptr(ws, p.g_off);
@@ -693,22 +667,14 @@ cpra_status cpra_train_step(const cpra_csr* g, const cpra_step_cfg* cfg, float* 
   } else if (step_counter) {
     CPRA_CHECK(increment_counter(step_counter, st));
   }
-  // CPRA_FUSED_EMB_ADAM=1: the embedding's Adam update runs in the epilogue of the
-  // product that emits its gradient (a transform-first layer 0), and the Adam
-  // pass below covers the layer weights only
-  const int32_t* stop = es ? &cfg->early_stop.state->stopped : nullptr;
-  const AdamEpi emb_adam = adam_epi(&cfg->adam, params, m, v, t, step_counter, 0, stop);
-  const bool want_fused = fused_emb_adam_enabled() && p.train_from == 0;
-  bool fused = false;
   CPRA_CHECK(backward_impl(g, p, params, dZ, S, grads, ws, st, side, true,
-                           side && terms ? &terms_task : nullptr, want_fused ? &emb_adam : nullptr,
-                           &fused));
+                           side && terms ? &terms_task : nullptr));
   if (side) CPRA_CHECK(join_from(side, st));
-  // only the trainable tail [first trained layer, end) when the encoder is frozen,
-  // and past the embedding when its update was fused
-  const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : (fused ? p.layer[0].off_ws : 0);
+  // only the trainable tail [first trained layer, end) when the encoder is frozen
+  const int64_t a0 = p.train_from > 0 ? p.layer[p.train_from].off_ws : 0;
   CPRA_CHECK(adam_step(p.n_params - a0, params + a0, grads + a0, m + a0, v + a0, &cfg->adam, t,
-                       step_counter, st, /*t_offset=*/0, stop));
+                       step_counter, st, /*t_offset=*/0,
+                       es ? &cfg->early_stop.state->stopped : nullptr));
   return CPRA_OK;
 }
 

@@ -421,86 +421,6 @@ def test_fork_orders_and_one_stream_are_bit_identical(preset, monkeypatch):
             assert torch.equal(x, y), f"{other}: {what}"
 
 
-FUSED_ADAM_CASES = [("C3s", False), ("C3s", True), ("C4", False), ("C2", False), ("one_layer", False)]
-
-
-@pytest.mark.parametrize("case,per_graph", FUSED_ADAM_CASES,
-                         ids=[f"{c}{'_per_graph' if pg else ''}" for c, pg in FUSED_ADAM_CASES])
-def test_fused_embedding_adam_is_bit_identical(case, per_graph, monkeypatch):
-    """CPRA_FUSED_EMB_ADAM=1 applies the embedding's Adam update in the epilogue of
-    the product that emits its gradient (layer 0's input gradient) and leaves the
-    layer weights to the Adam pass; both orders of the layer-0 work and the shared
-    element update give the same bits as the separate pass: three replayed steps
-    with early stopping armed (GCN on a ragged ER batch, shared and per-graph
-    weights; three GCN layers; GraphSAGE with bias gradients; a one-layer model,
-    whose loss-term task never forks)."""
-    api, CPRAConfig, CPRASolver = mods()
-    if case == "one_layer":
-        g = random_regular_graph(3000, 5, 21)
-        kind, layers, hidden, S, lam = "gcn", 1, 16, 16, np.logspace(-1, 1, 16).astype(np.float32)
-        cfg = CPRAConfig(problem="mis", layer_kind=kind, n_layers=layers, hidden=hidden, S=S)
-    else:
-        pr = get_preset(case)
-        g = pr.graph()
-        kind, layers, hidden, S, lam = pr.layer_kind, pr.n_layers, pr.hidden, pr.S, pr.lam
-        cfg = CPRAConfig(problem=pr.problem, layer_kind=kind, n_layers=layers, hidden=hidden, S=S,
-                         alpha=pr.alpha, nu=pr.nu, T=pr.T, per_graph_weights=per_graph)
-    dg = api.DeviceGraph.from_csr(g)
-    if per_graph:
-        from workloads import init_params_per_graph
-        p = init_params_per_graph(kind, g.n, layers, hidden, S, g.n_graphs, seed=6)
-    else:
-        p = init_params(kind, g.n, layers, hidden, S, seed=6)
-    out = {}
-    for fused in ("0", "1"):
-        monkeypatch.setenv("CPRA_FUSED_EMB_ADAM", fused)
-        sol = CPRASolver(dg, cfg, lam)
-        sol.load_params(p)
-        sol.enable_early_stopping(tol=1e-5, patience=1000)
-        sol.run(3, use_graph=True)
-        sol.step()  # and one eager step
-        torch.cuda.synchronize()
-        out[fused] = [x.clone() for x in (sol.params, sol.m, sol.v, sol.Z, sol.terms, sol.step_counter)]
-        sol.close()
-    for what, x, y in zip(("params", "m", "v", "Z", "terms", "step counter"), out["0"], out["1"]):
-        assert torch.equal(x, y), what
-
-
-def test_fused_embedding_adam_under_the_tuner_updates_once(monkeypatch):
-    """The autotuner re-runs each product while timing it; with the embedding's Adam
-    update in an epilogue it times the product without the update and then runs
-    the chosen plan once with it.  A tuned fused step equals an unfused step with
-    the plans the tuner chose, bit for bit."""
-    api, CPRAConfig, CPRASolver = mods()
-    pr = get_preset("C3s")
-    g = pr.graph()
-    dg = api.DeviceGraph.from_csr(g)
-    cfg = CPRAConfig(problem=pr.problem, layer_kind=pr.layer_kind, n_layers=pr.n_layers,
-                     hidden=pr.hidden, S=pr.S, alpha=pr.alpha, nu=pr.nu, T=pr.T)
-    p = init_params(pr.layer_kind, g.n, pr.n_layers, pr.hidden, pr.S, seed=8)
-    try:
-        monkeypatch.setenv("CPRA_FUSED_EMB_ADAM", "1")
-        api.autotune_reset()
-        a = CPRASolver(dg, cfg, pr.lam)
-        a.load_params(p)
-        a.autotune()
-        plans = api.autotune_table()
-        monkeypatch.setenv("CPRA_FUSED_EMB_ADAM", "0")
-        api.autotune_reset()
-        for e in plans:
-            api.autotune_set(e["key"], e["cfg"], e["splits"])
-        b = CPRASolver(dg, cfg, pr.lam)
-        b.load_params(p)
-        b.step()
-        torch.cuda.synchronize()
-        for what, x, y in zip(("params", "m", "v"), (a.params, a.m, a.v), (b.params, b.m, b.v)):
-            assert torch.equal(x, y), what
-        a.close()
-        b.close()
-    finally:
-        api.autotune_reset()
-
-
 def test_multi_step_graph_replays_equal_one_step_replays():
     """Ten steps replayed through a graph of four recorded steps (two launches, then
     two launches of the one-step graph) give the same bits as ten one-step
