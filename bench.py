@@ -62,12 +62,19 @@ def build_workload(name: str, per_graph: bool = False):
     return pr, g, params
 
 
+FORK_ORDER = "preset"  # --fork-order: "preset", "main" (input gradient first) or "side"
+
+
+def side_first(pr) -> bool:
+    return pr.side_first if FORK_ORDER == "preset" else FORK_ORDER == "side"
+
+
 def make_solver(pr, g, params, per_graph: bool = False, edge_weight=None):
     from paper_2402_02190_amd import api
     from paper_2402_02190_amd.solver import CPRAConfig, CPRASolver
     # capture order of the backward's forks, chosen per workload by step time (the
     # library reads the switch whenever it records a step)
-    if pr.side_first:
+    if side_first(pr):
         os.environ["CPRA_SIDE_FIRST"] = "1"
     else:
         os.environ.pop("CPRA_SIDE_FIRST", None)
@@ -354,7 +361,7 @@ def step_benchmark(workload: str, args, per_graph: bool, instances, instance_dro
                    "n_edges": g.n_edges, "n_graphs": g.n_graphs, "S": pr.S,
                    "layer": pr.layer_kind, "layers": pr.n_layers, "hidden": pr.hidden,
                    "problem": pr.problem, "recompute": bool(pr.recompute),
-                   "backward_fork_order": "side work first" if pr.side_first else "input gradient first",
+                   "backward_fork_order": "side work first" if side_first(pr) else "input gradient first",
                    "hip_graph_replay": True, "steps_per_graph": args.graph_steps,
                    "per_graph_weights": bool(per_graph),
                    "autotuned_gemm": not args.no_autotune,
@@ -428,6 +435,9 @@ def main():
     ap.add_argument("--tuning-file", default=None,
                     help="GEMM tuning table: loaded if it exists, else written after autotuning "
                          "(default: the committed MI355X table of the workload, if any)")
+    ap.add_argument("--fork-order", choices=("preset", "main", "side"), default="preset",
+                    help="capture order at the backward's forks: the workload preset's choice, the "
+                         "input gradient first, or the side-stream work first")
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="training steps recorded in one HIP graph for the replays (one graph "
                          "launch per that many steps; a one-step graph runs the remainder)")
@@ -437,6 +447,8 @@ def main():
                     help="instead of the step benchmark: time the fused loss kernel and the "
                          "aggregation alone on near-20-regular graphs of these sizes, S = 64")
     args = ap.parse_args()
+    global FORK_ORDER
+    FORK_ORDER = args.fork_order
     if args.loss_sweep is not None:
         sizes = args.loss_sweep or [100_000, 400_000, 1_000_000, 4_000_000]
         rows = loss_sweep(sizes)
