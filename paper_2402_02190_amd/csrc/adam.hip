@@ -39,7 +39,34 @@ __device__ inline void adam_one(float& p, float g, float& m, float& v, const Ada
   p = p * c.decay - c.lr * mhat / denom;
 }
 
-template <bool VEC4>
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// float4 load / store, streaming (nontemporal) when NT: every element is read
+// and written once per step, so the vectors need not stay in the caches.
+template <bool NT>
+__device__ inline float4 ld4(const float4* p) {
+  if constexpr (NT) {
+    const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    return make_float4(x.x, x.y, x.z, x.w);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ inline void st4(float4* p, const float4& v) {
+  if constexpr (NT) {
+    f4v x;
+    x.x = v.x;
+    x.y = v.y;
+    x.z = v.z;
+    x.w = v.w;
+    __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+  } else {
+    *p = v;
+  }
+}
+
+template <bool VEC4, bool NT = false>
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   if (a.stop_flag && *a.stop_flag) return;  // uniform across the grid
   __shared__ float s_bc[2];
@@ -61,15 +88,15 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     float4* m4 = reinterpret_cast<float4*>(a.m);
     float4* v4 = reinterpret_cast<float4*>(a.v);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-      float4 p = p4[i], m = m4[i], v = v4[i];
-      const float4 g = g4[i];
+      float4 p = ld4<NT>(p4 + i), m = ld4<NT>(m4 + i), v = ld4<NT>(v4 + i);
+      const float4 g = ld4<NT>(g4 + i);
       adam_one(p.x, g.x, m.x, v.x, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.y, g.y, m.y, v.y, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.z, g.z, m.z, v.z, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.w, g.w, m.w, v.w, c, inv_bc1, inv_sqrt_bc2);
-      p4[i] = p;
-      m4[i] = m;
-      v4[i] = v;
+      st4<NT>(p4 + i, p);
+      st4<NT>(m4 + i, m);
+      st4<NT>(v4 + i, v);
     }
     for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride)
       adam_one(a.p[i], a.g[i], a.m[i], a.v[i], c, inv_bc1, inv_sqrt_bc2);
@@ -96,7 +123,12 @@ cpra_status adam_step(int64_t n, float* params, const float* grads, float* m, fl
   const int64_t work = vec ? (n + 3) / 4 : n;
   const int blocks = (int)std::min<int64_t>(ceil_div(work, 256), 256 * 8);
   ProfScope ps("adam", stream, 0.0, 28.0 * (double)n);
-  if (vec)
+  // streaming accesses once the four arrays exceed the L2s and most of the
+  // Infinity Cache
+  const bool nt = 16.0 * (double)n > 256.0 * 1024 * 1024;
+  if (vec && nt)
+    hipLaunchKernelGGL((k_adam<true, true>), dim3(blocks), dim3(256), 0, stream, a);
+  else if (vec)
     hipLaunchKernelGGL(k_adam<true>, dim3(blocks), dim3(256), 0, stream, a);
   else
     hipLaunchKernelGGL(k_adam<false>, dim3(blocks), dim3(256), 0, stream, a);
