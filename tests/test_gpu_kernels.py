@@ -442,6 +442,39 @@ def test_gemm_every_tile_config_and_layout_matches_oracle(cfg):
         a.autotune_reset()
 
 
+@pytest.mark.parametrize("M,ring", [(4_000_000, True), (8_400_000, False)])
+def test_gemm_ring_offsets_and_fallback_past_2gib(M, ring):
+    """The LDS-ring loop addresses its operands with 32-bit byte offsets: an A of
+    1.0 GB runs the ring configuration forced through the table, one of 2.15 GB
+    (past 2^31 bytes) its interleaved twin; the profiler names which one ran, and
+    sampled rows (the first, the last, and random ones in between) match FP64."""
+    a = api()
+    N = K = 64
+    torch.manual_seed(M)
+    A = torch.randn((M, K), dtype=torch.float32, device="cuda")
+    B = torch.randn((N, K), dtype=torch.float32, device="cuda")
+    C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    try:
+        a.autotune_reset()
+        a.autotune_set(f"NT|{M}x{N}x{K}", 27, 1)
+        a.profile_begin()
+        a.gemm(A, B, C, False, True)
+        torch.cuda.synchronize()
+        prof = a.profile_end()
+        fam = "gemm_nt_64x64x16_w2x2_ring" if ring else "gemm_nt_64x64x16_w2x2_il"
+        assert fam in prof, sorted(prof)
+        rows = np.unique(np.concatenate([[0, 1, M - 2, M - 1],
+                                         np.random.default_rng(M).integers(0, M, 2000)]))
+        idx = torch.as_tensor(rows, device="cuda")
+        As = A[idx].cpu().numpy().astype(np.float64)
+        ref = As @ B.cpu().numpy().astype(np.float64).T
+        assert_close_array(C[idx].cpu().numpy(), ref, 2e-6, f"M={M} sampled rows")
+    finally:
+        a.autotune_reset()
+        del A, C
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("M,cfg,splits", [(32, 27, 1024), (64, 27, 512), (32, 16, 1024), (64, 11, 512)])
 def test_gemm_committed_large_split_plans(M, cfg, splits):
     """The split-K plans of the committed 256-graph tuning table at their real shape
