@@ -41,8 +41,10 @@ __device__ inline void adam_one(float& p, float g, float& m, float& v, const Ada
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// float4 load / store, streaming (nontemporal) when NT: every element is read
-// and written once per step, so the vectors need not stay in the caches.
+// float4 load / store, streaming (nontemporal) when NT: the gradient and the
+// moments are read and written once per step and need not stay in the caches;
+// the parameters take ordinary accesses, since the next forward reads them
+// again (its first aggregation gathers the embedding).
 template <bool NT>
 __device__ inline float4 ld4(const float4* p) {
   if constexpr (NT) {
@@ -88,13 +90,13 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     float4* m4 = reinterpret_cast<float4*>(a.m);
     float4* v4 = reinterpret_cast<float4*>(a.v);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-      float4 p = ld4<NT>(p4 + i), m = ld4<NT>(m4 + i), v = ld4<NT>(v4 + i);
+      float4 p = p4[i], m = ld4<NT>(m4 + i), v = ld4<NT>(v4 + i);
       const float4 g = ld4<NT>(g4 + i);
       adam_one(p.x, g.x, m.x, v.x, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.y, g.y, m.y, v.y, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.z, g.z, m.z, v.z, c, inv_bc1, inv_sqrt_bc2);
       adam_one(p.w, g.w, m.w, v.w, c, inv_bc1, inv_sqrt_bc2);
-      st4<NT>(p4 + i, p);
+      p4[i] = p;  // the next forward gathers the parameters (the embedding) again
       st4<NT>(m4 + i, m);
       st4<NT>(v4 + i, v);
     }
